@@ -1,0 +1,250 @@
+"""FP64 CPU oracle (test infrastructure only).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of ``bench.py`` may
+import this package. The product library never imports it and shares no code with it.
+
+Every routine is a ctypes call into ``oracle.c`` (plain C, double precision), compiled with gcc by
+:func:`build`. The C file's header lists which section / algorithm of Boukaram et al.,
+"Batched QR and SVD Algorithms on GPUs with Applications in Hierarchical Matrix Compression"
+(arXiv:1707.05141) each routine follows.
+
+Arrays are numpy float64, column-major (Fortran order) per instance.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+_D = ctypes.POINTER(ctypes.c_double)
+_I = ctypes.POINTER(ctypes.c_int)
+_U32 = ctypes.POINTER(ctypes.c_uint32)
+
+
+def build(force: bool = True) -> str:
+    """Compile ``oracle.c`` into ``liboracle.so`` with gcc (OpenMP across instances)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        build(force=True)
+    lib = ctypes.CDLL(_LIB)
+    lib.oracle_qr.argtypes = [ctypes.c_int, ctypes.c_int, _D, ctypes.c_int, _D, ctypes.c_int, _D, ctypes.c_int]
+    lib.oracle_jacobi_svd.argtypes = [ctypes.c_int, ctypes.c_int, _D, ctypes.c_int, ctypes.c_double,
+                                      ctypes.c_int, _D, _D, ctypes.c_int, _D, ctypes.c_int, _I]
+    lib.oracle_philox4x32_10.argtypes = [_U32, _U32, _U32]
+    lib.oracle_gauss.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32]
+    lib.oracle_gauss.restype = ctypes.c_double
+    lib.oracle_rank_rule.argtypes = [ctypes.c_int, _D, ctypes.c_double, ctypes.c_double, _D]
+    lib.oracle_rsvd_fixed.argtypes = [ctypes.c_int, ctypes.c_int, _D, ctypes.c_int, ctypes.c_int,
+                                      ctypes.c_uint64, ctypes.c_uint32, ctypes.c_double, ctypes.c_double,
+                                      ctypes.c_int, _I, _D, _D, ctypes.c_int, _D, ctypes.c_int, _D]
+    lib.oracle_rsvd_adaptive.argtypes = [ctypes.c_int, ctypes.c_int, _D, ctypes.c_int, ctypes.c_int,
+                                         ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_uint64,
+                                         ctypes.c_uint32, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                         _I, _D, _D, ctypes.c_int, _D, ctypes.c_int, _D, _I, _I]
+    lib.oracle_mlp_nparam.restype = ctypes.c_int
+    lib.oracle_mlp_forward.argtypes = [ctypes.c_int, _D, _D, _D]
+    lib.oracle_mlp_loss_grad.argtypes = [ctypes.c_int, _D, _D, _D, _D]
+    lib.oracle_mlp_loss_grad.restype = ctypes.c_double
+    lib.oracle_batched_jacobi_svd.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _D, ctypes.c_double,
+                                              ctypes.c_int, _D, _D, _D, _I, _I]
+    lib.oracle_batched_qr.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _D, _D, _D, _I]
+    lib.oracle_num_threads.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(_D) if a is not None else None
+
+
+def _f64(A):
+    return np.asfortranarray(np.asarray(A, dtype=np.float64))
+
+
+def qr(A):
+    """Householder QR (Algorithm 1). Returns thin Q (m x k) and R (k x n), k = min(m, n)."""
+    lib = _load()
+    A = _f64(A)
+    m, n = A.shape
+    k = min(m, n)
+    Q = np.zeros((m, k), order="F")
+    R = np.zeros((k, n), order="F")
+    rc = lib.oracle_qr(m, n, _dp(A), m, _dp(Q), m, _dp(R), k)
+    if rc != 0:
+        raise ValueError("oracle_qr: bad arguments")
+    return Q, R
+
+
+def jacobi_svd(A, tol=1e-15, max_sweeps=60):
+    """One-sided Jacobi SVD (Algorithm 2). Returns (S, U, V, sweeps, info)."""
+    lib = _load()
+    A = _f64(A)
+    m, n = A.shape
+    k = min(m, n)
+    S = np.zeros(k)
+    U = np.zeros((m, k), order="F")
+    V = np.zeros((n, k), order="F")
+    sw = ctypes.c_int(0)
+    info = lib.oracle_jacobi_svd(m, n, _dp(A), m, tol, max_sweeps, _dp(S), _dp(U), m, _dp(V), n,
+                                 ctypes.byref(sw))
+    if info < 0:
+        raise ValueError("oracle_jacobi_svd: bad arguments")
+    return S, U, V, sw.value, info
+
+
+def batched_jacobi_svd(A, tol=1e-15, max_sweeps=60, want_vectors=True):
+    """Jacobi SVD of a uniform batch A[b, m, n] (instances on OpenMP threads)."""
+    lib = _load()
+    A = np.asarray(A, dtype=np.float64)
+    bsz, m, n = A.shape
+    k = min(m, n)
+    Af = np.ascontiguousarray(np.transpose(A, (0, 2, 1)))  # each instance column-major
+    S = np.zeros((bsz, k))
+    U = np.zeros((bsz, k, m)) if want_vectors else None
+    V = np.zeros((bsz, k, n)) if want_vectors else None
+    sw = np.zeros(bsz, dtype=np.int32)
+    info = np.zeros(bsz, dtype=np.int32)
+    lib.oracle_batched_jacobi_svd(bsz, m, n, _dp(Af), tol, max_sweeps, _dp(S), _dp(U), _dp(V),
+                                  sw.ctypes.data_as(_I), info.ctypes.data_as(_I))
+    if want_vectors:
+        U = np.transpose(U, (0, 2, 1))
+        V = np.transpose(V, (0, 2, 1))
+    return S, U, V, sw, info
+
+
+def batched_qr(A):
+    """Householder QR of a uniform batch A[b, m, n]. Returns Q[b, m, k], R[b, k, n]."""
+    lib = _load()
+    A = np.asarray(A, dtype=np.float64)
+    bsz, m, n = A.shape
+    k = min(m, n)
+    Af = np.ascontiguousarray(np.transpose(A, (0, 2, 1)))
+    Q = np.zeros((bsz, k, m))
+    R = np.zeros((bsz, n, k))
+    info = np.zeros(bsz, dtype=np.int32)
+    lib.oracle_batched_qr(bsz, m, n, _dp(Af), _dp(Q), _dp(R), info.ctypes.data_as(_I))
+    return np.transpose(Q, (0, 2, 1)), np.transpose(R, (0, 2, 1))
+
+
+def philox4x32_10(ctr, key):
+    lib = _load()
+    c = (ctypes.c_uint32 * 4)(*[int(x) & 0xFFFFFFFF for x in ctr])
+    k = (ctypes.c_uint32 * 2)(*[int(x) & 0xFFFFFFFF for x in key])
+    o = (ctypes.c_uint32 * 4)()
+    lib.oracle_philox4x32_10(c, k, o)
+    return [o[i] for i in range(4)]
+
+
+def gauss(seed, inst, col, row):
+    return _load().oracle_gauss(int(seed) & (2**64 - 1), inst, col, row)
+
+
+def omega(seed, inst, n, ncols, col0=0):
+    """The n x ncols sampling matrix (columns col0 .. col0+ncols-1 of the counter stream)."""
+    lib = _load()
+    out = np.empty((n, ncols))
+    for c in range(ncols):
+        for r in range(n):
+            out[r, c] = lib.oracle_gauss(int(seed) & (2**64 - 1), inst, col0 + c, r)
+    return out
+
+
+def rank_rule(sigma, normA2, eps):
+    """Smallest k with resid2 + sum_{i>=k} sigma_i^2 <= eps^2 normA2 (Section 8.2)."""
+    lib = _load()
+    s = np.ascontiguousarray(sigma, dtype=np.float64)
+    tail = ctypes.c_double(0)
+    k = lib.oracle_rank_rule(len(s), _dp(s), float(normA2), float(eps), ctypes.byref(tail))
+    return k, tail.value
+
+
+def rsvd_fixed(A, ell, seed, inst=0, eps=1e-6, tol=1e-15, max_rank=None):
+    """Algorithm 4 with ell samples. Returns dict(rank, S, U, V, err_est, info)."""
+    lib = _load()
+    A = _f64(A)
+    m, n = A.shape
+    if max_rank is None:
+        max_rank = ell
+    S = np.zeros(ell)
+    U = np.zeros((m, ell), order="F")
+    V = np.zeros((n, ell), order="F")
+    rank = ctypes.c_int(0)
+    err = ctypes.c_double(0)
+    info = lib.oracle_rsvd_fixed(m, n, _dp(A), m, ell, int(seed) & (2**64 - 1), inst, eps, tol, max_rank,
+                                 ctypes.byref(rank), _dp(S), _dp(U), m, _dp(V), n, ctypes.byref(err))
+    if info < 0:
+        raise ValueError("oracle_rsvd_fixed: bad arguments")
+    k = rank.value
+    return dict(rank=k, S=S[:k].copy(), U=U[:, :k].copy(), V=V[:, :k].copy(), err_est=err.value, info=info)
+
+
+def rsvd_adaptive(A, seed, inst=0, eps=1e-6, ell0=0, blk=8, cap=None, safety=2.0, tol=1e-15, max_rank=None):
+    """Adaptive range finder + exact check + second phase of Algorithm 4.
+
+    Returns dict(rank, S, U, V, err_est, info, ell, rounds)."""
+    lib = _load()
+    A = _f64(A)
+    m, n = A.shape
+    kmin = min(m, n)
+    if cap is None or cap <= 0 or cap > kmin:
+        cap = kmin
+    if max_rank is None:
+        max_rank = cap
+    S = np.zeros(cap)
+    U = np.zeros((m, cap), order="F")
+    V = np.zeros((n, cap), order="F")
+    rank = ctypes.c_int(0)
+    err = ctypes.c_double(0)
+    ell = ctypes.c_int(0)
+    rounds = ctypes.c_int(0)
+    info = lib.oracle_rsvd_adaptive(m, n, _dp(A), m, ell0, blk, cap, safety, int(seed) & (2**64 - 1), inst,
+                                    eps, tol, max_rank, ctypes.byref(rank), _dp(S), _dp(U), m, _dp(V), n,
+                                    ctypes.byref(err), ctypes.byref(ell), ctypes.byref(rounds))
+    if info < 0:
+        raise ValueError("oracle_rsvd_adaptive: bad arguments")
+    k = rank.value
+    return dict(rank=k, S=S[:k].copy(), U=U[:, :k].copy(), V=V[:, :k].copy(), err_est=err.value, info=info,
+                ell=ell.value, rounds=rounds.value)
+
+
+MLP_NPARAM = 5313
+
+
+def mlp_forward(params, X):
+    lib = _load()
+    p = np.ascontiguousarray(params, dtype=np.float64)
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    out = np.zeros(X.shape[0])
+    lib.oracle_mlp_forward(X.shape[0], _dp(p), _dp(X), _dp(out))
+    return out
+
+
+def mlp_loss_grad(params, X, y):
+    lib = _load()
+    p = np.ascontiguousarray(params, dtype=np.float64)
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    g = np.zeros(MLP_NPARAM)
+    loss = lib.oracle_mlp_loss_grad(X.shape[0], _dp(p), _dp(X), _dp(y), _dp(g))
+    return loss, g
+
+
+def num_threads():
+    return _load().oracle_num_threads()

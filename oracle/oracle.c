@@ -1,0 +1,617 @@
+/*
+ * FP64 CPU oracle for batched QR, one-sided Jacobi SVD and randomized SVD.
+ *
+ * TEST INFRASTRUCTURE ONLY. The product library never includes, links, loads or calls this
+ * file; only the test-suite, the smoke check and the CPU-baseline leg of the benchmark do.
+ * It shares no code, header, table or constant with the GPU library.
+ *
+ * Written from W. H. Boukaram, G. Turkiyyah, H. Ltaief, D. E. Keyes, "Batched QR and SVD
+ * Algorithms on GPUs with Applications in Hierarchical Matrix Compression" (arXiv:1707.05141):
+ *   oracle_qr            Householder QR, Section 2.1, Algorithm 1 (reflectors applied one at a
+ *                        time to R from the left and accumulated into Q from the right).
+ *   oracle_jacobi_svd    One-sided (Hestenes) Jacobi SVD, Section 2.2, Algorithm 2: sweeps over
+ *                        all column pairs, 2x2 Gram, plane rotation, until the columns are
+ *                        mutually orthogonal; singular values are the column norms, left vectors
+ *                        the normalised columns, right vectors the accumulated rotations.
+ *   oracle_rsvd_fixed    Two-phase randomized SVD, Section 7.1, Algorithm 4.
+ *   oracle_rsvd_adaptive Same second phase, with the first phase grown block by block until an
+ *                        a-posteriori residual test passes (adaptive range finder of Halko,
+ *                        Martinsson, Tropp, SIAM Review 53(2), 2011, Sections 4.3-4.4; the paper
+ *                        defers robust range finders to that reference in Section 7.1).
+ *   oracle_rank_rule     Truncation at a relative Frobenius threshold, Section 8.2 (the truncated
+ *                        factor must satisfy ||A - A_k||_F <= eps ||A||_F).
+ *   oracle_philox/gauss  Counter-based Gaussian sampling matrix Omega (Section 7.1 draws a Gaussian
+ *                        sampling matrix; the counter generator is Philox4x32-10 of Salmon, Moraes,
+ *                        Dror, Shaw, SC'11, and the Gaussian map is Box-Muller).
+ *   oracle_mlp_*         Reference forward/backward of the 16-64-64-1 ReLU rank-prediction network.
+ *
+ * Readings where the paper is silent (each listed in the design notes of the repository):
+ *   - house(): beta = -sign(alpha)*||x|| with sign(0)=+1; a length-1 or already-zero sub-column
+ *     gets H = I, so R's diagonal can be negative.
+ *   - rot(G): Rutishauser's small-angle rotation, zeta=(beta-alpha)/(2 gamma),
+ *     t = sign(zeta)/(|zeta|+sqrt(1+zeta^2)), c = 1/sqrt(1+t^2), s = c t.
+ *   - convergence: a pair is skipped when |gamma| <= tol*sqrt(alpha)*sqrt(beta); a sweep with no
+ *     rotation ends the iteration; max_sweeps caps it (info = 1).
+ *   - pair order: row-cyclic (0,1),(0,2),...,(n-2,n-1).
+ *   - m < n: the SVD of A^T is computed and U, V swap roles.
+ *
+ * Storage: column-major with a leading dimension; every routine is single-threaded per instance,
+ * the batched wrappers run instances on OpenMP threads.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORACLE_INFO_OK 0
+#define ORACLE_INFO_SWEEPS 1   /* sweep cap reached */
+#define ORACLE_INFO_RANKCAP 2  /* rank capacity reached before the tolerance was met */
+#define ORACLE_INFO_NONFINITE 3
+
+static int all_finite(int m, int n, const double *A, int lda) {
+    for (int j = 0; j < n; ++j)
+        for (int i = 0; i < m; ++i)
+            if (!isfinite(A[i + (size_t)j * lda])) return 0;
+    return 1;
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Householder QR (Section 2.1, Algorithm 1).                                                  */
+/* Full Q (m x m) starts as I and R as A; for each column j a unit vector v is built from the  */
+/* sub-column R(j:m, j); R <- (I - 2 v v^T) R and Q <- Q (I - 2 v v^T). Returns the thin Q     */
+/* (first k = min(m,n) columns) and the k x n upper trapezoidal R with exact zeros below the   */
+/* diagonal.                                                                                    */
+/* ------------------------------------------------------------------------------------------ */
+int oracle_qr(int m, int n, const double *A, int lda, double *Q, int ldq, double *R, int ldr) {
+    if (m < 1 || n < 1 || lda < m) return -1;
+    int k = m < n ? m : n;
+    double *Rf = (double *)malloc(sizeof(double) * (size_t)m * n);
+    double *Qf = (double *)malloc(sizeof(double) * (size_t)m * m);
+    double *v = (double *)malloc(sizeof(double) * (size_t)m);
+    double *w = (double *)malloc(sizeof(double) * (size_t)(m > n ? m : n));
+    for (int j = 0; j < n; ++j)
+        for (int i = 0; i < m; ++i) Rf[i + (size_t)j * m] = A[i + (size_t)j * lda];
+    for (int j = 0; j < m; ++j)
+        for (int i = 0; i < m; ++i) Qf[i + (size_t)j * m] = (i == j) ? 1.0 : 0.0;
+
+    for (int j = 0; j < k; ++j) {
+        int len = m - j;
+        if (len < 2) continue; /* length-1 sub-column: H = I */
+        double alpha = Rf[j + (size_t)j * m];
+        double s2 = 0.0;
+        for (int i = j + 1; i < m; ++i) s2 += Rf[i + (size_t)j * m] * Rf[i + (size_t)j * m];
+        if (s2 == 0.0) continue; /* already upper triangular in this column: H = I */
+        double nu = sqrt(alpha * alpha + s2);
+        double beta = (alpha >= 0.0) ? -nu : nu;
+        /* v = x - beta e1, normalised */
+        v[0] = alpha - beta;
+        for (int i = 1; i < len; ++i) v[i] = Rf[j + i + (size_t)j * m];
+        double vn2 = v[0] * v[0] + s2;
+        double vn = sqrt(vn2);
+        for (int i = 0; i < len; ++i) v[i] /= vn;
+        /* R(j:m, j:n) -= 2 v (v^T R(j:m, j:n)) */
+        for (int c = j; c < n; ++c) {
+            double d = 0.0;
+            for (int i = 0; i < len; ++i) d += v[i] * Rf[j + i + (size_t)c * m];
+            w[c] = d;
+        }
+        for (int c = j; c < n; ++c)
+            for (int i = 0; i < len; ++i) Rf[j + i + (size_t)c * m] -= 2.0 * v[i] * w[c];
+        /* Q(:, j:m) -= 2 (Q(:, j:m) v) v^T */
+        for (int r = 0; r < m; ++r) {
+            double d = 0.0;
+            for (int i = 0; i < len; ++i) d += Qf[r + (size_t)(j + i) * m] * v[i];
+            w[r] = d;
+        }
+        for (int i = 0; i < len; ++i)
+            for (int r = 0; r < m; ++r) Qf[r + (size_t)(j + i) * m] -= 2.0 * w[r] * v[i];
+    }
+    if (Q)
+        for (int j = 0; j < k; ++j)
+            for (int i = 0; i < m; ++i) Q[i + (size_t)j * ldq] = Qf[i + (size_t)j * m];
+    if (R)
+        for (int j = 0; j < n; ++j)
+            for (int i = 0; i < k; ++i) R[i + (size_t)j * ldr] = (i <= j) ? Rf[i + (size_t)j * m] : 0.0;
+    free(Rf); free(Qf); free(v); free(w);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* One-sided Jacobi SVD (Section 2.2, Algorithm 2).                                            */
+/* ------------------------------------------------------------------------------------------ */
+
+/* rot(G) for G = [[alpha, gamma], [gamma, beta]]: returns (c, s) such that the rotated columns
+ * c*w_i - s*w_j and s*w_i + c*w_j are orthogonal in exact arithmetic. */
+static void jacobi_rotation(double alpha, double beta, double gamma, double *c, double *s) {
+    double zeta = (beta - alpha) / (2.0 * gamma);
+    double t;
+    if (fabs(zeta) > 1e150) {
+        t = 0.5 / zeta; /* 1/(2 zeta): the limit of the formula below, without overflow */
+    } else {
+        double sg = (zeta >= 0.0) ? 1.0 : -1.0;
+        t = sg / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+    }
+    *c = 1.0 / sqrt(1.0 + t * t);
+    *s = (*c) * t;
+}
+
+/* Jacobi on an M x N working matrix W (M >= N), accumulating the N x N right rotations VV.
+ * Returns the number of sweeps executed and sets *converged. */
+static int jacobi_core(int M, int N, double *W, double *VV, double tol, int max_sweeps, int *converged) {
+    int sweep = 0;
+    *converged = 0;
+    while (sweep < max_sweeps) {
+        ++sweep;
+        int rotated = 0;
+        for (int i = 0; i < N - 1; ++i) {
+            for (int j = i + 1; j < N; ++j) {
+                double *wi = W + (size_t)i * M, *wj = W + (size_t)j * M;
+                double alpha = 0.0, beta = 0.0, gamma = 0.0;
+                for (int r = 0; r < M; ++r) {
+                    alpha += wi[r] * wi[r];
+                    beta += wj[r] * wj[r];
+                    gamma += wi[r] * wj[r];
+                }
+                if (alpha == 0.0 || beta == 0.0) continue;
+                if (fabs(gamma) <= tol * sqrt(alpha) * sqrt(beta)) continue;
+                double c, s;
+                jacobi_rotation(alpha, beta, gamma, &c, &s);
+                for (int r = 0; r < M; ++r) {
+                    double a = wi[r], b = wj[r];
+                    wi[r] = c * a - s * b;
+                    wj[r] = s * a + c * b;
+                }
+                double *vi = VV + (size_t)i * N, *vj = VV + (size_t)j * N;
+                for (int r = 0; r < N; ++r) {
+                    double a = vi[r], b = vj[r];
+                    vi[r] = c * a - s * b;
+                    vj[r] = s * a + c * b;
+                }
+                ++rotated;
+            }
+        }
+        if (rotated == 0) { *converged = 1; break; }
+    }
+    return sweep;
+}
+
+/* SVD of an m x n matrix A. Outputs (k = min(m,n)): S[k] descending, U (m x k, ldu),
+ * V (n x k, ldv); U or V may be NULL. Returns info: 0 ok, 1 sweep cap, 3 non-finite input,
+ * negative for bad arguments. *sweeps_out (nullable) receives the sweeps executed. */
+int oracle_jacobi_svd(int m, int n, const double *A, int lda, double tol, int max_sweeps,
+                      double *S, double *U, int ldu, double *V, int ldv, int *sweeps_out) {
+    if (m < 1 || n < 1 || lda < m) return -1;
+    if (max_sweeps <= 0) max_sweeps = 60;
+    int k = m < n ? m : n;
+    int trans = m < n;
+    int M = trans ? n : m, N = k;
+    if (!all_finite(m, n, A, lda)) {
+        for (int i = 0; i < k; ++i) S[i] = NAN;
+        if (sweeps_out) *sweeps_out = 0;
+        return ORACLE_INFO_NONFINITE;
+    }
+    double *W = (double *)malloc(sizeof(double) * (size_t)M * N);
+    double *VV = (double *)malloc(sizeof(double) * (size_t)N * N);
+    double *sig = (double *)malloc(sizeof(double) * (size_t)N);
+    int *perm = (int *)malloc(sizeof(int) * (size_t)N);
+    for (int j = 0; j < N; ++j)
+        for (int i = 0; i < M; ++i)
+            W[i + (size_t)j * M] = trans ? A[j + (size_t)i * lda] : A[i + (size_t)j * lda];
+    for (int j = 0; j < N; ++j)
+        for (int i = 0; i < N; ++i) VV[i + (size_t)j * N] = (i == j) ? 1.0 : 0.0;
+
+    int converged;
+    int sweeps = jacobi_core(M, N, W, VV, tol, max_sweeps, &converged);
+
+    for (int j = 0; j < N; ++j) {
+        double s2 = 0.0;
+        for (int i = 0; i < M; ++i) s2 += W[i + (size_t)j * M] * W[i + (size_t)j * M];
+        sig[j] = sqrt(s2);
+        perm[j] = j;
+    }
+    /* stable insertion sort of column indices by descending norm */
+    for (int a = 1; a < N; ++a) {
+        int p = perm[a];
+        int b = a - 1;
+        while (b >= 0 && sig[perm[b]] < sig[p]) { perm[b + 1] = perm[b]; --b; }
+        perm[b + 1] = p;
+    }
+    /* left factor of the working matrix = normalised columns; right factor = VV */
+    double *Lout = trans ? V : U;
+    int ldl = trans ? ldv : ldu;
+    double *Rout = trans ? U : V;
+    int ldrr = trans ? ldu : ldv;
+    for (int c = 0; c < N; ++c) {
+        int p = perm[c];
+        double sp = sig[p];
+        S[c] = sp;
+        if (Lout)
+            for (int i = 0; i < M; ++i)
+                Lout[i + (size_t)c * ldl] = (sp > 0.0) ? W[i + (size_t)p * M] / sp : 0.0;
+        if (Rout)
+            for (int i = 0; i < N; ++i) Rout[i + (size_t)c * ldrr] = VV[i + (size_t)p * N];
+    }
+    if (sweeps_out) *sweeps_out = sweeps;
+    free(W); free(VV); free(sig); free(perm);
+    return converged ? ORACLE_INFO_OK : ORACLE_INFO_SWEEPS;
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Counter-based Gaussian sampling (Philox4x32-10 + Box-Muller).                               */
+/* Philox4x32 round: (L0,R0,L1,R1) with multipliers M0, M1; hi/lo of the 64-bit products are  */
+/* mixed with the other words and the round key; keys are bumped by the Weyl constants.       */
+/* ------------------------------------------------------------------------------------------ */
+void oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+    uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int r = 0; r < 10; ++r) {
+        uint64_t p0 = (uint64_t)0xD2511F53u * x0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * x2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t y0 = hi1 ^ x1 ^ k0;
+        uint32_t y1 = lo1;
+        uint32_t y2 = hi0 ^ x3 ^ k1;
+        uint32_t y3 = lo0;
+        x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+/* Entry (row, col) of the sampling matrix of instance `inst`: counter = (row, col, inst, 0),
+ * key = the two halves of the 64-bit seed. Two 53-bit uniforms in (0,1) from the four words,
+ * then z = sqrt(-2 ln u1) cos(2 pi u2). */
+double oracle_gauss(uint64_t seed, uint32_t inst, uint32_t col, uint32_t row) {
+    uint32_t ctr[4] = {row, col, inst, 0u};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t o[4];
+    oracle_philox4x32_10(ctr, key, o);
+    uint64_t a = (((uint64_t)o[0] << 32) | o[1]) >> 11;
+    uint64_t b = (((uint64_t)o[2] << 32) | o[3]) >> 11;
+    double u1 = ((double)a + 0.5) * 0x1.0p-53;
+    double u2 = ((double)b + 0.5) * 0x1.0p-53;
+    return sqrt(-2.0 * log(u1)) * cos(6.283185307179586476925286766559 * u2);
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Truncation rule (Section 8.2): smallest k such that                                         */
+/*   resid2 + sum_{i >= k} sigma_i^2 <= eps^2 * normA2,                                        */
+/* with resid2 = max(0, normA2 - sum_i sigma_i^2) the part of ||A||_F^2 outside the factored  */
+/* subspace (zero for a full SVD) and the tail summed from the smallest sigma upward.          */
+/* ------------------------------------------------------------------------------------------ */
+int oracle_rank_rule(int nsig, const double *sigma, double normA2, double eps, double *tail_out) {
+    double tot = 0.0;
+    for (int i = nsig - 1; i >= 0; --i) tot += sigma[i] * sigma[i];
+    double resid2 = normA2 - tot;
+    if (resid2 < 0.0) resid2 = 0.0;
+    double thr = eps * eps * normA2;
+    /* tail[k] = resid2 + sum_{i>=k} sigma_i^2, built from the smallest upward */
+    double tail = resid2;
+    int k = nsig;
+    double tail_at_k = resid2;
+    if (tail <= thr) {
+        for (int i = nsig - 1; i >= 0; --i) {
+            double t2 = tail + sigma[i] * sigma[i];
+            if (t2 <= thr) { tail = t2; k = i; tail_at_k = t2; }
+            else break;
+        }
+    } else {
+        k = nsig; /* tolerance not reachable with these sigma: keep everything */
+        tail_at_k = resid2;
+    }
+    if (tail_out) *tail_out = tail_at_k;
+    return k;
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Randomized SVD helpers.                                                                     */
+/* ------------------------------------------------------------------------------------------ */
+static double frob2(int m, int n, const double *A, int lda) {
+    double s = 0.0;
+    for (int j = 0; j < n; ++j)
+        for (int i = 0; i < m; ++i) s += A[i + (size_t)j * lda] * A[i + (size_t)j * lda];
+    return s;
+}
+
+/* Y(:, 0:b) = A * Omega(:, col0 : col0+b) with Omega drawn from the counter generator. */
+static void sketch(int m, int n, const double *A, int lda, uint64_t seed, uint32_t inst, int col0,
+                   int b, double *Y, int ldy) {
+    double *om = (double *)malloc(sizeof(double) * (size_t)n);
+    for (int c = 0; c < b; ++c) {
+        for (int r = 0; r < n; ++r) om[r] = oracle_gauss(seed, inst, (uint32_t)(col0 + c), (uint32_t)r);
+        for (int i = 0; i < m; ++i) {
+            double s = 0.0;
+            for (int r = 0; r < n; ++r) s += A[i + (size_t)r * lda] * om[r];
+            Y[i + (size_t)c * ldy] = s;
+        }
+    }
+    free(om);
+}
+
+/* Second phase of Section 7.1 given an orthonormal m x ell basis Q:
+ * B = Q^T A (ell x n); [Q_B, R_B] = qr(B^T); [U_R, S, V_R] = svd(R_B^T);
+ * U = Q U_R, V = Q_B V_R; truncate with the rank rule. Writes up to max_rank columns. */
+static int rsvd_second_phase(int m, int n, const double *A, int lda, const double *Q, int ell,
+                             double normA2, double eps, double tol, int max_rank, int *rank,
+                             double *S, double *U, int ldu, double *V, int ldv, double *err_est,
+                             int *check_ok) {
+    double *B = (double *)malloc(sizeof(double) * (size_t)ell * n);
+    double *Bt = (double *)malloc(sizeof(double) * (size_t)n * ell);
+    double *QB = (double *)malloc(sizeof(double) * (size_t)n * ell);
+    double *RB = (double *)malloc(sizeof(double) * (size_t)ell * ell);
+    double *RBt = (double *)malloc(sizeof(double) * (size_t)ell * ell);
+    double *UR = (double *)malloc(sizeof(double) * (size_t)ell * ell);
+    double *VR = (double *)malloc(sizeof(double) * (size_t)ell * ell);
+    double *sg = (double *)malloc(sizeof(double) * (size_t)ell);
+    for (int j = 0; j < n; ++j)
+        for (int i = 0; i < ell; ++i) {
+            double s = 0.0;
+            for (int r = 0; r < m; ++r) s += Q[r + (size_t)i * m] * A[r + (size_t)j * lda];
+            B[i + (size_t)j * ell] = s;
+        }
+    /* exact a-posteriori check: ||A - Q Q^T A||_F^2 = ||A||_F^2 - ||B||_F^2 */
+    double b2 = frob2(ell, n, B, ell);
+    if (check_ok) *check_ok = (normA2 - b2) <= eps * eps * normA2;
+    for (int j = 0; j < ell; ++j)
+        for (int i = 0; i < n; ++i) Bt[i + (size_t)j * n] = B[j + (size_t)i * ell];
+    oracle_qr(n, ell, Bt, n, QB, n, RB, ell);
+    for (int j = 0; j < ell; ++j)
+        for (int i = 0; i < ell; ++i) RBt[i + (size_t)j * ell] = RB[j + (size_t)i * ell];
+    int info = oracle_jacobi_svd(ell, ell, RBt, ell, tol, 0, sg, UR, ell, VR, ell, NULL);
+    double tail;
+    int k = oracle_rank_rule(ell, sg, normA2, eps, &tail);
+    int kk = k < max_rank ? k : max_rank;
+    if (k > max_rank) info = ORACLE_INFO_RANKCAP;
+    *rank = kk;
+    for (int c = 0; c < kk; ++c) {
+        S[c] = sg[c];
+        if (U)
+            for (int i = 0; i < m; ++i) {
+                double s = 0.0;
+                for (int r = 0; r < ell; ++r) s += Q[i + (size_t)r * m] * UR[r + (size_t)c * ell];
+                U[i + (size_t)c * ldu] = s;
+            }
+        if (V)
+            for (int i = 0; i < n; ++i) {
+                double s = 0.0;
+                for (int r = 0; r < ell; ++r) s += QB[i + (size_t)r * n] * VR[r + (size_t)c * ell];
+                V[i + (size_t)c * ldv] = s;
+            }
+    }
+    if (err_est) {
+        double t = 0.0;
+        if (kk < k) {
+            /* capacity-limited: tail includes the dropped sigma */
+            double tot = 0.0;
+            for (int i = ell - 1; i >= kk; --i) tot += sg[i] * sg[i];
+            double all = 0.0;
+            for (int i = ell - 1; i >= 0; --i) all += sg[i] * sg[i];
+            double resid2 = normA2 - all;
+            if (resid2 < 0) resid2 = 0;
+            t = resid2 + tot;
+        } else {
+            t = tail;
+        }
+        *err_est = normA2 > 0.0 ? sqrt(t / normA2) : 0.0;
+    }
+    free(B); free(Bt); free(QB); free(RB); free(RBt); free(UR); free(VR); free(sg);
+    return info;
+}
+
+/* Randomized SVD with a fixed number ell of samples (Section 7.1, Algorithm 4):
+ * Omega = columns 0..ell-1 of the counter stream; Y = A Omega; Q = qr(Y); then the second
+ * phase. ell must satisfy 1 <= ell <= min(m, n). Returns info (0, 2 = rank cap, 3 non-finite). */
+int oracle_rsvd_fixed(int m, int n, const double *A, int lda, int ell, uint64_t seed, uint32_t inst,
+                      double eps, double tol, int max_rank, int *rank, double *S, double *U, int ldu,
+                      double *V, int ldv, double *err_est) {
+    int kmin = m < n ? m : n;
+    if (m < 1 || n < 1 || lda < m || ell < 1 || ell > kmin) return -1;
+    if (!all_finite(m, n, A, lda)) { *rank = 0; return ORACLE_INFO_NONFINITE; }
+    double normA2 = frob2(m, n, A, lda);
+    double *Y = (double *)malloc(sizeof(double) * (size_t)m * ell);
+    double *Q = (double *)malloc(sizeof(double) * (size_t)m * ell);
+    double *Ry = (double *)malloc(sizeof(double) * (size_t)ell * ell);
+    sketch(m, n, A, lda, seed, inst, 0, ell, Y, m);
+    oracle_qr(m, ell, Y, m, Q, m, Ry, ell);
+    int info = rsvd_second_phase(m, n, A, lda, Q, ell, normA2, eps, tol, max_rank, rank, S, U, ldu,
+                                 V, ldv, err_est, NULL);
+    free(Y); free(Q); free(Ry);
+    return info;
+}
+
+/* Adaptive range finder + a-posteriori check, then the second phase.
+ * The basis starts from `ell0` samples (0 = none) and grows by blocks of `blk` columns of the
+ * counter stream (column indices continue where the previous block ended). For each new block
+ * Y_b = A Omega_b is projected against the current basis twice (classical Gram-Schmidt, twice),
+ * est2 = mean_j ||Y_b(:,j)||^2 is an unbiased estimate of ||(I - QQ^T) A||_F^2 for Gaussian
+ * columns; the orthonormalised block is appended to Q, and growth stops once
+ * est2 <= (eps/safety)^2 ||A||_F^2 or the capacity cap is met. The exact test
+ * ||A||_F^2 - ||Q^T A||_F^2 <= eps^2 ||A||_F^2 then decides; on failure growth resumes.
+ * `cap` bounds the basis size (<= min(m,n)). *ell_out receives the final basis size and
+ * *rounds_out the number of sampling blocks drawn after the initial one. */
+int oracle_rsvd_adaptive(int m, int n, const double *A, int lda, int ell0, int blk, int cap,
+                         double safety, uint64_t seed, uint32_t inst, double eps, double tol,
+                         int max_rank, int *rank, double *S, double *U, int ldu, double *V, int ldv,
+                         double *err_est, int *ell_out, int *rounds_out) {
+    int kmin = m < n ? m : n;
+    if (m < 1 || n < 1 || lda < m || blk < 1 || ell0 < 0) return -1;
+    if (cap > kmin || cap <= 0) cap = kmin;
+    if (ell0 > cap) ell0 = cap;
+    if (!all_finite(m, n, A, lda)) { *rank = 0; return ORACLE_INFO_NONFINITE; }
+    double normA2 = frob2(m, n, A, lda);
+    double *Q = (double *)malloc(sizeof(double) * (size_t)m * cap);
+    double *Y = (double *)malloc(sizeof(double) * (size_t)m * (cap > blk ? cap : blk));
+    double *Qb = (double *)malloc(sizeof(double) * (size_t)m * (cap > blk ? cap : blk));
+    double *Rb = (double *)malloc(sizeof(double) * (size_t)cap * cap + (size_t)blk * blk);
+    double *h = (double *)malloc(sizeof(double) * (size_t)cap);
+    int ell = 0, rounds = 0;
+    double thr = (eps / safety) * (eps / safety) * normA2;
+    if (ell0 > 0) {
+        sketch(m, n, A, lda, seed, inst, 0, ell0, Y, m);
+        oracle_qr(m, ell0, Y, m, Q, m, Rb, ell0);
+        ell = ell0;
+    }
+    int info = 0, last_ok = 0;
+    for (;;) {
+        int check_ok = 0;
+        if (ell > 0) {
+            /* exact test on the current basis (computed inside the second phase) */
+            info = rsvd_second_phase(m, n, A, lda, Q, ell, normA2, eps, tol, max_rank, rank, S, U,
+                                     ldu, V, ldv, err_est, &check_ok);
+            last_ok = check_ok;
+            if (check_ok || ell >= cap) break;
+        }
+        /* grow until the estimator says the residual is small */
+        for (;;) {
+            int b = blk < cap - ell ? blk : cap - ell;
+            sketch(m, n, A, lda, seed, inst, ell, b, Y, m);
+            ++rounds;
+            for (int pass = 0; pass < 2; ++pass) {
+                for (int c = 0; c < b; ++c) {
+                    double *y = Y + (size_t)c * m;
+                    for (int q = 0; q < ell; ++q) {
+                        double d = 0.0;
+                        for (int i = 0; i < m; ++i) d += Q[i + (size_t)q * m] * y[i];
+                        h[q] = d;
+                    }
+                    for (int q = 0; q < ell; ++q)
+                        for (int i = 0; i < m; ++i) y[i] -= Q[i + (size_t)q * m] * h[q];
+                }
+            }
+            double est2 = 0.0;
+            for (int c = 0; c < b; ++c)
+                for (int i = 0; i < m; ++i) est2 += Y[i + (size_t)c * m] * Y[i + (size_t)c * m];
+            est2 /= (double)b;
+            oracle_qr(m, b, Y, m, Qb, m, Rb, b);
+            for (int c = 0; c < b; ++c)
+                for (int i = 0; i < m; ++i) Q[i + (size_t)(ell + c) * m] = Qb[i + (size_t)c * m];
+            ell += b;
+            if (est2 <= thr || ell >= cap) break;
+        }
+    }
+    if (info == ORACLE_INFO_OK && !last_ok) info = ORACLE_INFO_RANKCAP;
+    if (ell_out) *ell_out = ell;
+    if (rounds_out) *rounds_out = rounds;
+    free(Q); free(Y); free(Qb); free(Rb); free(h);
+    return info;
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Rank-prediction network 16 -> 64 -> 64 -> 1 with ReLU hidden layers and MSE loss.          */
+/* Parameter vector layout (5313 doubles): W1[64][16], b1[64], W2[64][64], b2[64], W3[64],    */
+/* b3[1]; W[o][i] row-major (output-major).                                                    */
+/* ------------------------------------------------------------------------------------------ */
+#define MLP_IN 16
+#define MLP_H 64
+#define MLP_NPARAM (MLP_H * MLP_IN + MLP_H + MLP_H * MLP_H + MLP_H + MLP_H + 1)
+
+int oracle_mlp_nparam(void) { return MLP_NPARAM; }
+
+/* Forward for N samples X[N][16] -> out[N]. */
+void oracle_mlp_forward(int N, const double *p, const double *X, double *out) {
+    const double *W1 = p, *b1 = W1 + MLP_H * MLP_IN, *W2 = b1 + MLP_H, *b2 = W2 + MLP_H * MLP_H;
+    const double *W3 = b2 + MLP_H, *b3 = W3 + MLP_H;
+    double h1[MLP_H], h2[MLP_H];
+    for (int s = 0; s < N; ++s) {
+        const double *x = X + (size_t)s * MLP_IN;
+        for (int o = 0; o < MLP_H; ++o) {
+            double a = b1[o];
+            for (int i = 0; i < MLP_IN; ++i) a += W1[o * MLP_IN + i] * x[i];
+            h1[o] = a > 0.0 ? a : 0.0;
+        }
+        for (int o = 0; o < MLP_H; ++o) {
+            double a = b2[o];
+            for (int i = 0; i < MLP_H; ++i) a += W2[o * MLP_H + i] * h1[i];
+            h2[o] = a > 0.0 ? a : 0.0;
+        }
+        double a = b3[0];
+        for (int i = 0; i < MLP_H; ++i) a += W3[i] * h2[i];
+        out[s] = a;
+    }
+}
+
+/* Loss L = (1/N) sum_s (f(x_s) - y_s)^2 and its gradient dL/dp (grad may be NULL). */
+double oracle_mlp_loss_grad(int N, const double *p, const double *X, const double *y, double *grad) {
+    const double *W1 = p, *b1 = W1 + MLP_H * MLP_IN, *W2 = b1 + MLP_H, *b2 = W2 + MLP_H * MLP_H;
+    const double *W3 = b2 + MLP_H, *b3 = W3 + MLP_H;
+    double *gW1 = grad, *gb1 = grad ? gW1 + MLP_H * MLP_IN : NULL, *gW2 = grad ? gb1 + MLP_H : NULL;
+    double *gb2 = grad ? gW2 + MLP_H * MLP_H : NULL, *gW3 = grad ? gb2 + MLP_H : NULL;
+    double *gb3 = grad ? gW3 + MLP_H : NULL;
+    if (grad) memset(grad, 0, sizeof(double) * MLP_NPARAM);
+    double a1[MLP_H], h1[MLP_H], a2[MLP_H], h2[MLP_H], d2[MLP_H], d1[MLP_H];
+    double loss = 0.0;
+    for (int s = 0; s < N; ++s) {
+        const double *x = X + (size_t)s * MLP_IN;
+        for (int o = 0; o < MLP_H; ++o) {
+            double a = b1[o];
+            for (int i = 0; i < MLP_IN; ++i) a += W1[o * MLP_IN + i] * x[i];
+            a1[o] = a; h1[o] = a > 0.0 ? a : 0.0;
+        }
+        for (int o = 0; o < MLP_H; ++o) {
+            double a = b2[o];
+            for (int i = 0; i < MLP_H; ++i) a += W2[o * MLP_H + i] * h1[i];
+            a2[o] = a; h2[o] = a > 0.0 ? a : 0.0;
+        }
+        double f = b3[0];
+        for (int i = 0; i < MLP_H; ++i) f += W3[i] * h2[i];
+        double r = f - y[s];
+        loss += r * r;
+        if (!grad) continue;
+        double df = 2.0 * r / (double)N;
+        gb3[0] += df;
+        for (int i = 0; i < MLP_H; ++i) {
+            gW3[i] += df * h2[i];
+            d2[i] = (a2[i] > 0.0) ? df * W3[i] : 0.0;
+        }
+        for (int o = 0; o < MLP_H; ++o) {
+            gb2[o] += d2[o];
+            for (int i = 0; i < MLP_H; ++i) gW2[o * MLP_H + i] += d2[o] * h1[i];
+        }
+        for (int i = 0; i < MLP_H; ++i) {
+            double d = 0.0;
+            for (int o = 0; o < MLP_H; ++o) d += W2[o * MLP_H + i] * d2[o];
+            d1[i] = (a1[i] > 0.0) ? d : 0.0;
+        }
+        for (int o = 0; o < MLP_H; ++o) {
+            gb1[o] += d1[o];
+            for (int i = 0; i < MLP_IN; ++i) gW1[o * MLP_IN + i] += d1[o] * x[i];
+        }
+    }
+    return loss / (double)N;
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Batched wrappers: uniform-shape batches stored back to back (stride = ld * cols). Instances */
+/* run on OpenMP threads; each instance is independent.                                        */
+/* ------------------------------------------------------------------------------------------ */
+void oracle_batched_jacobi_svd(int batch, int m, int n, const double *A, double tol, int max_sweeps,
+                               double *S, double *U, double *V, int *sweeps, int *info) {
+    int k = m < n ? m : n;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int b = 0; b < batch; ++b) {
+        info[b] = oracle_jacobi_svd(m, n, A + (size_t)b * m * n, m, tol, max_sweeps, S + (size_t)b * k,
+                                    U ? U + (size_t)b * m * k : NULL, m,
+                                    V ? V + (size_t)b * n * k : NULL, n, sweeps ? sweeps + b : NULL);
+    }
+}
+
+void oracle_batched_qr(int batch, int m, int n, const double *A, double *Q, double *R, int *info) {
+    int k = m < n ? m : n;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int b = 0; b < batch; ++b)
+        info[b] = oracle_qr(m, n, A + (size_t)b * m * n, m, Q ? Q + (size_t)b * m * k : NULL, m,
+                            R ? R + (size_t)b * k * n : NULL, k);
+}
+
+int oracle_num_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

@@ -1,0 +1,99 @@
+"""Seeded synthetic inputs shaped like the paper's workloads.
+
+This module only draws inputs: it holds none of the factorisation arithmetic and is shared by the
+tests, the benchmark and the oracle comparisons. Every batch is reproducible from
+(workload, instance, seed). Matrices are returned as float64 numpy arrays; batches as [b, m, n]
+(row-major numpy layout of each instance; callers convert to column-major where needed).
+
+Workloads (all FP64, i.i.d. per instance):
+  * gaussian:   a_ij ~ N(0, 1)                                             (register-kernel batches)
+  * graded:     A = U diag(sigma) V^T with Haar U (m x n), V (n x n) and a prescribed spectrum
+                (the paper tests on matrices with prescribed condition numbers, Sections 4-6)
+  * kernel:     a_ij = exp(-|x_i - y_j| / 0.1) (exponential covariance, correlation length 0.1 as
+                in Section 8.3) or 1/|x_i - y_j|, x_i uniform in [0,1]^2, y_j uniform in
+                [2,3] x [0,1] (two unit squares whose centres are 2 apart): numerically low rank
+  * gauss_decay: U diag(exp(-(i/w)^2)) V^T with Haar U, V and a width w
+Haar matrices are the Q factor of a Gaussian matrix with the sign of diag(R) folded in
+(Mezzadri, Notices AMS 2007).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+SIZES_UNEVEN = (64, 128, 256, 512)
+
+
+def _rng(seed: int, inst: int, stream: int = 0) -> np.random.Generator:
+    return np.random.default_rng(np.random.SeedSequence([int(seed) & 0xFFFFFFFF, int(inst), int(stream)]))
+
+
+def haar(rng: np.random.Generator, m: int, n: int) -> np.ndarray:
+    """m x n matrix with orthonormal columns, Haar distributed (n <= m)."""
+    G = rng.standard_normal((m, n))
+    Q, R = np.linalg.qr(G)
+    d = np.sign(np.diag(R))
+    d[d == 0] = 1.0
+    return Q * d[None, :]
+
+
+def gaussian(m: int, n: int, seed: int, inst: int) -> np.ndarray:
+    return _rng(seed, inst).standard_normal((m, n))
+
+
+def graded_sigma_log(n: int, decades: float) -> np.ndarray:
+    """sigma_i = 10^(-decades (i-1)/(n-1)), i = 1..n (sigma_1 = 1, sigma_n = 10^-decades)."""
+    if n == 1:
+        return np.ones(1)
+    return 10.0 ** (-decades * np.arange(n) / (n - 1))
+
+
+def prescribed(m: int, n: int, sigma: np.ndarray, seed: int, inst: int) -> np.ndarray:
+    """A = U diag(sigma) V^T with Haar U, V; len(sigma) = min(m, n)."""
+    rng = _rng(seed, inst)
+    k = min(m, n)
+    U = haar(rng, m, k)
+    V = haar(rng, n, k)
+    return (U * sigma[None, :]) @ V.T
+
+
+def kernel_points(m: int, n: int, seed: int, inst: int):
+    rng = _rng(seed, inst, 1)
+    x = rng.random((m, 2))
+    y = rng.random((n, 2))
+    y[:, 0] += 2.0
+    return x, y
+
+
+def kernel_block(m: int, n: int, seed: int, inst: int, kind: str = "exp", corr: float = 0.1) -> np.ndarray:
+    x, y = kernel_points(m, n, seed, inst)
+    d = np.sqrt(((x[:, None, :] - y[None, :, :]) ** 2).sum(-1))
+    if kind == "exp":
+        return np.exp(-d / corr)
+    if kind == "inv":
+        return 1.0 / d
+    raise ValueError(kind)
+
+
+def gauss_decay(m: int, n: int, w: float, seed: int, inst: int) -> np.ndarray:
+    k = min(m, n)
+    sigma = np.exp(-((np.arange(1, k + 1) / w) ** 2))
+    return prescribed(m, n, sigma, seed, inst)
+
+
+def uneven_shapes(count: int, seed: int, sizes=SIZES_UNEVEN):
+    """m, n drawn i.i.d. uniformly from `sizes` (the uneven batch of low-rank blocks)."""
+    rng = _rng(seed, 0, 7)
+    m = rng.choice(np.asarray(sizes), size=count)
+    n = rng.choice(np.asarray(sizes), size=count)
+    return m.astype(np.int32), n.astype(np.int32)
+
+
+# --- batch builders for the named workloads -----------------------------------------------------
+
+def batch_gaussian(batch: int, m: int, n: int, seed: int = 1) -> np.ndarray:
+    return np.stack([gaussian(m, n, seed, i) for i in range(batch)])
+
+
+def batch_graded(batch: int, m: int, n: int, decades: float, seed: int = 2) -> np.ndarray:
+    s = graded_sigma_log(min(m, n), decades)
+    return np.stack([prescribed(m, n, s, seed, i) for i in range(batch)])

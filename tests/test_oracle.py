@@ -1,0 +1,398 @@
+"""Pins of the FP64 CPU oracle against facts fixed by the paper and by the mathematics.
+
+Nothing here touches the GPU library. Each test is chosen so that a plausible slip in the oracle
+(a dropped term, a wrong sign or index, a transposed operand) fails at least one of them:
+closed forms, prescribed spectra, invariants, brute force on tiny inputs, library special cases.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1707_05141_amd import synth
+
+U64 = np.finfo(np.float64).eps
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _golden_cases():
+    out = []
+    with open(os.path.join(GOLDEN, "svd_closed_form.txt")) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            shape, ents, sig = [p.strip() for p in line.split("|")]
+            m, n = map(int, shape.split())
+            A = np.array([float(x) for x in ents.split()]).reshape(m, n)
+            s = np.array([eval(x, {"sqrt": math.sqrt}) for x in sig.split()])
+            out.append((A, s))
+    return out
+
+
+# ---------------------------------------------------------------- one-sided Jacobi (Algorithm 2)
+
+@pytest.mark.parametrize("case", range(len(_golden_cases())))
+def test_jacobi_closed_form_golden(case):
+    A, s = _golden_cases()[case]
+    S, U, V, sw, info = oracle.jacobi_svd(A)
+    assert info == 0
+    np.testing.assert_allclose(S, s, rtol=0, atol=8 * U64 * max(1.0, s[0]))
+
+
+def test_jacobi_2x2_closed_form_random():
+    rng = np.random.default_rng(11)
+    for _ in range(200):
+        a, b, c, d = rng.standard_normal(4) * 10.0 ** rng.uniform(-3, 3)
+        A = np.array([[a, b], [c, d]])
+        S, U, V, sw, info = oracle.jacobi_svd(A)
+        # (s1 +- s2)^2 = ||A||_F^2 +- 2|det A|; the two roots below swap roles when det A < 0
+        r1 = math.sqrt((a + d) ** 2 + (c - b) ** 2)
+        r2 = math.sqrt((a - d) ** 2 + (b + c) ** 2)
+        ssum, sdif = max(r1, r2), min(r1, r2)
+        scale = max(ssum, 1e-300)
+        assert abs((S[0] + S[1]) - ssum) <= 8 * U64 * scale
+        assert abs((S[0] - S[1]) - sdif) <= 8 * U64 * scale
+
+
+def test_single_rotation_orthogonalises_pair():
+    """One rotation of an m x 2 matrix leaves the pair orthogonal to rounding (rot(G) of Alg. 2)."""
+    rng = np.random.default_rng(3)
+    for _ in range(50):
+        A = rng.standard_normal((17, 2)) @ np.array([[1.0, 0.9], [0.0, 0.1]])
+        S, U, V, sw, info = oracle.jacobi_svd(A, max_sweeps=1)
+        # one sweep = one rotation; columns of U are the normalised rotated columns
+        g = abs(U[:, 0] @ U[:, 1])
+        assert g <= 20 * U64
+        # V is a plane rotation: orthogonal with det +1 up to the column sort
+        assert abs(abs(np.linalg.det(V)) - 1) < 1e-14
+        np.testing.assert_allclose(U * S[None, :] @ V.T, A, atol=20 * U64 * np.linalg.norm(A))
+
+
+@pytest.mark.parametrize("m,n,decades", [(32, 32, 0.0), (32, 32, 8.0), (64, 64, 8.0), (128, 32, 8.0),
+                                         (33, 17, 4.0), (17, 33, 4.0)])
+def test_jacobi_prescribed_spectrum(m, n, decades):
+    k = min(m, n)
+    sigma = synth.graded_sigma_log(k, decades)
+    for inst in range(3):
+        A = synth.prescribed(m, n, sigma, seed=5, inst=inst)
+        S, U, V, sw, info = oracle.jacobi_svd(A)
+        assert info == 0
+        assert np.all(np.diff(S) <= 0)
+        assert np.max(np.abs(S - sigma)) <= 4 * max(m, n) * U64 * sigma[0]
+        # invariants: orthonormal factors, reconstruction, Frobenius identity
+        assert np.linalg.norm(V.T @ V - np.eye(k)) <= 4 * k * U64 * 10
+        assert np.linalg.norm(A - (U * S[None, :]) @ V.T) <= 10 * k * U64 * np.linalg.norm(A)
+        assert abs((S ** 2).sum() - (A ** 2).sum()) <= 10 * k * U64 * (A ** 2).sum()
+        # left vectors of well-separated singular values are orthonormal
+        good = S > 1e-6 * S[0]
+        Ug = U[:, good]
+        assert np.linalg.norm(Ug.T @ Ug - np.eye(good.sum())) <= 1e-9
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 8])
+def test_jacobi_bruteforce_eig_AtA(n):
+    """Tiny inputs: sigma^2 are the eigenvalues of A^T A (definition of the SVD, Section 1)."""
+    rng = np.random.default_rng(n)
+    for _ in range(10):
+        m = n + int(rng.integers(0, 4))
+        A = rng.standard_normal((m, n))
+        S, U, V, sw, info = oracle.jacobi_svd(A)
+        ev = np.sort(np.linalg.eigvalsh(A.T @ A))[::-1]
+        np.testing.assert_allclose(S ** 2, ev, rtol=0, atol=50 * U64 * ev[0])
+        # A v_i = sigma_i u_i
+        np.testing.assert_allclose(A @ V, U * S[None, :], atol=20 * n * U64 * S[0])
+
+
+@pytest.mark.parametrize("m,n", [(1, 1), (1, 5), (5, 1), (7, 3), (3, 7), (40, 40), (64, 20), (20, 64)])
+def test_jacobi_vs_library_svd(m, n):
+    rng = np.random.default_rng(m * 100 + n)
+    A = rng.standard_normal((m, n))
+    S, U, V, sw, info = oracle.jacobi_svd(A)
+    assert info == 0
+    ref = np.linalg.svd(A, compute_uv=False)
+    np.testing.assert_allclose(S, ref, rtol=0, atol=20 * max(m, n) * U64 * ref[0])
+    np.testing.assert_allclose(U * S[None, :] @ V.T, A, atol=50 * max(m, n) * U64 * ref[0])
+
+
+def test_jacobi_zero_columns_and_rank_deficient():
+    rng = np.random.default_rng(9)
+    A = rng.standard_normal((10, 6))
+    A[:, 2] = 0.0
+    A[:, 4] = 2.0 * A[:, 1]
+    S, U, V, sw, info = oracle.jacobi_svd(A)
+    assert info == 0
+    ref = np.linalg.svd(A, compute_uv=False)
+    np.testing.assert_allclose(S, ref, atol=1e-13 * ref[0])
+    # the exactly-zero column has sigma 0 and a zero left vector
+    assert S[-1] == 0.0
+    assert np.all(U[:, -1] == 0.0)
+    np.testing.assert_allclose(U * S[None, :] @ V.T, A, atol=1e-13 * ref[0])
+
+
+def test_jacobi_nonfinite_and_sweep_cap():
+    A = np.eye(4)
+    A[1, 2] = np.nan
+    S, U, V, sw, info = oracle.jacobi_svd(A)
+    assert info == 3
+    rng = np.random.default_rng(1)
+    A = rng.standard_normal((32, 32))
+    S, U, V, sw, info = oracle.jacobi_svd(A, max_sweeps=2)
+    assert info == 1 and sw == 2
+    S, U, V, sw, info = oracle.jacobi_svd(A)
+    assert info == 0 and 5 <= sw <= 15
+
+
+def test_jacobi_sorted_and_stable_ties():
+    A = np.diag([1.0, 3.0, 3.0, 2.0])
+    S, U, V, sw, info = oracle.jacobi_svd(A)
+    np.testing.assert_array_equal(S, [3.0, 3.0, 2.0, 1.0])
+    # already orthogonal: no rotation, columns come out in stable order (index 1 before 2)
+    assert sw == 1
+    np.testing.assert_array_equal(np.abs(V[:, 0]), [0, 1, 0, 0])
+    np.testing.assert_array_equal(np.abs(V[:, 1]), [0, 0, 1, 0])
+
+
+def test_batched_jacobi_matches_single():
+    A = synth.batch_gaussian(6, 12, 9, seed=4)
+    S, U, V, sw, info = oracle.batched_jacobi_svd(A)
+    for b in range(6):
+        s1, u1, v1, sw1, i1 = oracle.jacobi_svd(A[b])
+        np.testing.assert_array_equal(S[b], s1)
+        np.testing.assert_array_equal(U[b], u1)
+        np.testing.assert_array_equal(V[b], v1)
+        assert sw[b] == sw1 and info[b] == i1
+
+
+# ---------------------------------------------------------------- Householder QR (Algorithm 1)
+
+def test_qr_2x2_closed_form():
+    rng = np.random.default_rng(2)
+    for _ in range(100):
+        A = rng.standard_normal((2, 2))
+        Q, R = oracle.qr(A)
+        a1, a2 = A[:, 0], A[:, 1]
+        n1 = np.linalg.norm(a1)
+        # reading: beta = -sign(alpha) ||x||  =>  R11 = -sign(a11) ||a1||
+        assert abs(R[0, 0] - (-math.copysign(n1, a1[0]))) <= 4 * U64 * n1
+        assert abs(abs(R[0, 1]) - abs(a1 @ a2) / n1) <= 8 * U64 * np.linalg.norm(A)
+        assert abs(abs(R[1, 1]) - abs(np.linalg.det(A)) / n1) <= 8 * U64 * np.linalg.norm(A)
+        assert R[1, 0] == 0.0
+
+
+@pytest.mark.parametrize("m,n", [(1, 1), (1, 4), (4, 1), (2, 5), (8, 8), (64, 64), (128, 32), (33, 7), (7, 33),
+                                 (512, 24)])
+def test_qr_invariants(m, n):
+    rng = np.random.default_rng(m + 7 * n)
+    A = rng.standard_normal((m, n))
+    Q, R = oracle.qr(A)
+    k = min(m, n)
+    assert Q.shape == (m, k) and R.shape == (k, n)
+    assert np.all(np.tril(R, -1) == 0.0)
+    assert np.linalg.norm(Q.T @ Q - np.eye(k)) <= 10 * max(m, 4) * U64
+    assert np.linalg.norm(Q @ R - A) <= 10 * max(m, 4) * U64 * np.linalg.norm(A)
+
+
+@pytest.mark.parametrize("m,n", [(6, 4), (20, 20), (64, 16)])
+def test_qr_uniqueness_vs_cholesky(m, n):
+    """Sign-normalised R equals the Cholesky factor of A^T A (uniqueness of the QR factorisation)."""
+    rng = np.random.default_rng(m * n)
+    A = rng.standard_normal((m, n))
+    Q, R = oracle.qr(A)
+    D = np.sign(np.diag(R))
+    Rn = D[:, None] * R
+    L = np.linalg.cholesky(A.T @ A)
+    np.testing.assert_allclose(Rn, L.T, atol=1e-12 * np.linalg.norm(A))
+    np.testing.assert_allclose(Q * D[None, :], A @ np.linalg.inv(L.T), atol=1e-11)
+
+
+def test_qr_already_triangular_and_zero_column():
+    A = np.triu(np.arange(1.0, 17.0).reshape(4, 4))
+    Q, R = oracle.qr(A)
+    np.testing.assert_array_equal(Q, np.eye(4))
+    np.testing.assert_array_equal(R, A)
+    B = np.zeros((5, 3))
+    B[:, 1] = [1, 2, 3, 4, 5]
+    Q, R = oracle.qr(B)
+    assert np.linalg.norm(Q @ R - B) < 1e-13
+    assert np.linalg.norm(Q.T @ Q - np.eye(3)) < 1e-14
+
+
+# ---------------------------------------------------------------- rank rule (Section 8.2)
+
+def test_rank_rule_hand_cases():
+    # normA2 = 1 + 1e-6 + 1e-14 + 1e-16; eps^2 normA2 ~ 1e-12
+    s = np.array([1.0, 1e-3, 1e-7, 1e-8])
+    k, tail = oracle.rank_rule(s, (s ** 2).sum(), 1e-6)
+    assert k == 2
+    assert abs(tail - (1e-14 + 1e-16)) < 1e-28
+    # a zero matrix has rank 0
+    assert oracle.rank_rule(np.zeros(3), 0.0, 1e-6)[0] == 0
+    # equal singular values cannot be truncated at a small tolerance
+    assert oracle.rank_rule(np.ones(5), 5.0, 1e-3)[0] == 5
+    # eps = 1 truncates everything
+    assert oracle.rank_rule(np.array([2.0, 1.0]), 5.0, 1.0)[0] == 0
+    # mass outside the factored subspace (normA2 > sum sigma^2) counts against the tail
+    s = np.array([1.0, 1e-7])
+    assert oracle.rank_rule(s, 1.0 + 1e-14 + 5e-13, 1e-6)[0] == 1
+    assert oracle.rank_rule(s, 1.0 + 1e-14 + 2e-12, 1e-6)[0] == 2
+
+
+def test_rank_rule_eckart_young():
+    """The chosen k is the smallest whose truncated SVD meets ||A - A_k||_F <= eps ||A||_F."""
+    for inst in range(5):
+        A = synth.kernel_block(96, 80, seed=3, inst=inst)
+        U, S, Vt = np.linalg.svd(A, full_matrices=False)
+        eps = 1e-6
+        k, _ = oracle.rank_rule(S, (A ** 2).sum(), eps)
+        nA = np.linalg.norm(A)
+        err_k = np.linalg.norm(A - (U[:, :k] * S[:k]) @ Vt[:k])
+        err_km1 = np.linalg.norm(A - (U[:, :k - 1] * S[:k - 1]) @ Vt[:k - 1])
+        assert err_k <= eps * nA * (1 + 1e-6)
+        assert err_km1 > eps * nA * (1 - 1e-6)
+
+
+# ---------------------------------------------------------------- Gaussian sampling
+
+def test_gauss_statistics():
+    from scipy import stats
+    z = oracle.omega(seed=123, inst=7, n=500, ncols=100).ravel()
+    assert abs(z.mean()) < 0.02
+    assert abs(z.var() - 1.0) < 0.03
+    assert abs(stats.kurtosis(z, fisher=False) - 3.0) < 0.1
+    assert stats.kstest(z, "norm").pvalue > 1e-3
+    # different instances / seeds give uncorrelated columns
+    z2 = oracle.omega(seed=123, inst=8, n=500, ncols=100).ravel()
+    z3 = oracle.omega(seed=124, inst=7, n=500, ncols=100).ravel()
+    assert abs(np.corrcoef(z, z2)[0, 1]) < 0.03
+    assert abs(np.corrcoef(z, z3)[0, 1]) < 0.03
+
+
+def test_philox_is_a_keyed_bijection_sample():
+    outs = set()
+    for i in range(4000):
+        outs.add(tuple(oracle.philox4x32_10([i, 0, 0, 0], [1, 2])))
+    assert len(outs) == 4000
+    a = oracle.philox4x32_10([5, 6, 7, 8], [9, 10])
+    b = oracle.philox4x32_10([5, 6, 7, 8], [9, 11])
+    assert a != b
+    assert oracle.philox4x32_10([5, 6, 7, 8], [9, 10]) == a
+
+
+# ---------------------------------------------------------------- randomized SVD (Algorithm 4)
+
+def test_rsvd_exact_low_rank():
+    """Exact rank-r input with r <= ell: the sketch captures the range exactly."""
+    rng = np.random.default_rng(0)
+    m, n, r = 90, 70, 6
+    sig = np.array([5.0, 3.0, 1.0, 0.5, 0.1, 0.01])
+    U = synth.haar(rng, m, r)
+    V = synth.haar(rng, n, r)
+    A = (U * sig) @ V.T
+    # eps^2 must sit well above the FP64 rounding of ||A||_F^2 - sum sigma^2 (~u ||A||_F^2)
+    out = oracle.rsvd_fixed(A, ell=12, seed=1, eps=1e-6)
+    assert out["rank"] == r
+    np.testing.assert_allclose(out["S"], sig, rtol=0, atol=1e-13 * sig[0])
+    Ar = (out["U"] * out["S"]) @ out["V"].T
+    assert np.linalg.norm(Ar - A) <= 1e-13 * np.linalg.norm(A)
+    assert out["err_est"] <= 1e-7
+
+
+@pytest.mark.parametrize("m,n", [(64, 64), (128, 256), (256, 64), (512, 128)])
+def test_rsvd_kernel_blocks_meet_eps_and_exact_rank(m, n):
+    eps = 1e-6
+    for inst in range(2):
+        A = synth.kernel_block(m, n, seed=11, inst=inst)
+        U, S, Vt = np.linalg.svd(A, full_matrices=False)
+        k_exact, _ = oracle.rank_rule(S, (A ** 2).sum(), eps)
+        out = oracle.rsvd_adaptive(A, seed=99, inst=inst, eps=eps)
+        assert out["info"] == 0
+        Ar = (out["U"] * out["S"]) @ out["V"].T
+        err = np.linalg.norm(A - Ar) / np.linalg.norm(A)
+        assert err <= eps
+        assert abs(err - out["err_est"]) <= 1e-3 * eps
+        assert out["rank"] == k_exact
+        # interlacing: sigma_i(B) <= sigma_i(A)
+        assert np.all(out["S"] <= S[: out["rank"]] * (1 + 1e-12))
+        np.testing.assert_allclose(out["S"], S[: out["rank"]], rtol=0, atol=1e-8 * S[0])
+        # orthonormal factors
+        k = out["rank"]
+        assert np.linalg.norm(out["U"].T @ out["U"] - np.eye(k)) < 1e-12
+        assert np.linalg.norm(out["V"].T @ out["V"] - np.eye(k)) < 1e-12
+
+
+def test_rsvd_fixed_equals_adaptive_with_same_samples():
+    """A fixed-ell run and an adaptive run started from the same ell agree (same Omega columns)."""
+    A = synth.kernel_block(200, 150, seed=2, inst=0)
+    f = oracle.rsvd_fixed(A, ell=30, seed=5, eps=1e-6)
+    a = oracle.rsvd_adaptive(A, seed=5, eps=1e-6, ell0=30)
+    assert a["ell"] == 30 and a["rounds"] == 0
+    assert f["rank"] == a["rank"]
+    np.testing.assert_array_equal(f["S"], a["S"])
+
+
+def test_rsvd_adaptive_recovers_from_undersampling():
+    A = synth.kernel_block(256, 256, seed=4, inst=1)
+    small = oracle.rsvd_adaptive(A, seed=7, eps=1e-6, ell0=4)
+    assert small["rounds"] >= 1
+    Ar = (small["U"] * small["S"]) @ small["V"].T
+    assert np.linalg.norm(A - Ar) <= 1e-6 * np.linalg.norm(A)
+
+
+def test_rsvd_gauss_decay_rank_closed_form():
+    """U diag(exp(-(i/w)^2)) V^T: the exact truncation rank follows from the known spectrum."""
+    m, n, w, eps = 160, 120, 9.0, 1e-6
+    A = synth.gauss_decay(m, n, w, seed=3, inst=0)
+    sig = np.exp(-((np.arange(1, 121) / w) ** 2))
+    tail = np.cumsum((sig ** 2)[::-1])[::-1]  # tail[k] = sum_{i>=k} sigma_i^2 (0-based)
+    k_cf = int(np.argmax(np.append(tail, 0.0) <= eps ** 2 * (sig ** 2).sum()))
+    out = oracle.rsvd_adaptive(A, seed=1, eps=eps)
+    assert out["rank"] == k_cf
+
+
+def test_rsvd_rank_cap_and_nonfinite():
+    A = synth.kernel_block(128, 128, seed=1, inst=0)
+    out = oracle.rsvd_adaptive(A, seed=1, eps=1e-6, max_rank=3)
+    assert out["info"] == 2 and out["rank"] == 3
+    B = A.copy()
+    B[3, 3] = np.inf
+    assert oracle.rsvd_adaptive(B, seed=1, eps=1e-6)["info"] == 3
+
+
+# ---------------------------------------------------------------- rank-prediction network
+
+def test_mlp_forward_hand_weights():
+    p = np.zeros(oracle.MLP_NPARAM)
+    W1 = p[0:1024].reshape(64, 16)
+    b1 = p[1024:1088]
+    W2 = p[1088:5184].reshape(64, 64)
+    W3 = p[5248:5312]
+    W1[3, 5] = 1.0          # h1[3] = relu(x5)
+    b1[3] = -0.5            # ... - 0.5
+    W2[7, 3] = 2.0          # h2[7] = relu(2 h1[3])
+    W3[7] = 3.0
+    p[5312] = 0.25          # b3
+    X = np.zeros((3, 16))
+    X[:, 5] = [2.0, 0.2, -1.0]
+    X[:, 3] = [100.0, 100.0, 100.0]  # must be ignored
+    out = oracle.mlp_forward(p, X)
+    np.testing.assert_allclose(out, [3 * 2 * 1.5 + 0.25, 0.25, 0.25])
+
+
+def test_mlp_gradient_finite_differences():
+    rng = np.random.default_rng(0)
+    p = rng.standard_normal(oracle.MLP_NPARAM) * 0.3
+    X = rng.standard_normal((7, 16))
+    y = rng.standard_normal(7)
+    loss, g = oracle.mlp_loss_grad(p, X, y)
+    idx = rng.choice(oracle.MLP_NPARAM, 200, replace=False)
+    idx = np.concatenate([idx, [0, 1023, 1024, 1087, 1088, 5183, 5184, 5247, 5248, 5311, 5312]])
+    h = 1e-6
+    for i in idx:
+        pp = p.copy(); pp[i] += h
+        pm = p.copy(); pm[i] -= h
+        fd = (oracle.mlp_loss_grad(pp, X, y)[0] - oracle.mlp_loss_grad(pm, X, y)[0]) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(g[i])), (i, fd, g[i])
+    np.testing.assert_allclose(loss, np.mean((oracle.mlp_forward(p, X) - y) ** 2))
