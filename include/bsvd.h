@@ -1,0 +1,104 @@
+/*
+ * bsvd.h -- C ABI of the MI355X (gfx950) batched QR / one-sided Jacobi SVD / randomized SVD library.
+ *
+ * The operations are those of W. H. Boukaram, G. Turkiyyah, H. Ltaief, D. E. Keyes, "Batched QR and
+ * SVD Algorithms on GPUs with Applications in Hierarchical Matrix Compression" (arXiv:1707.05141):
+ * a batch is many independent small matrices resident in GPU memory, processed by one call per stage
+ * (Sections 1 and 2.3).
+ *
+ * Conventions shared by every entry point
+ *   - Matrices are column-major with a leading dimension (entry (i, j) of instance b lives at
+ *     ptr[b][i + j * ld[b]]), double precision unless a dtype argument says otherwise.
+ *   - Shape, leading-dimension, tolerance and rank arrays are HOST arrays of length `batch`.
+ *   - Matrix arguments are HOST arrays of length `batch` holding DEVICE pointers. The library copies
+ *     the pointer arrays into its own device workspace, so the caller may reuse them after return.
+ *   - Per-instance integer / scalar outputs (info, sweeps, rank, err_est) are DEVICE arrays of length
+ *     `batch` (nullable). They are written in stream order: read them after synchronising the stream.
+ *   - The caller owns every input and output buffer. Inputs are never overwritten.
+ *   - All work is enqueued on the context's stream; calls return without synchronising unless
+ *     stated otherwise. A context is not thread-safe; use one per host thread / stream.
+ *   - Batch-level validation happens on the host before anything is launched. A bad argument
+ *     returns BSVD_EARG and launches nothing; bsvd_last_error() names the instance and argument.
+ *   - Per-instance info codes: 0 ok; 1 sweep cap reached (results are the last iterate);
+ *     2 rank capacity reached before the tolerance was met; 3 non-finite input (outputs undefined,
+ *     S set to NaN).
+ */
+#ifndef BSVD_H
+#define BSVD_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bsvd_ctx bsvd_ctx;
+
+enum {
+    BSVD_OK = 0,
+    BSVD_EARG = -1,   /* invalid argument; nothing launched */
+    BSVD_EHIP = -2,   /* HIP runtime error */
+    BSVD_ENOMEM = -3, /* device or pinned-host allocation failed */
+    BSVD_EUNSUP = -4  /* shape / dtype / flag combination not supported */
+};
+
+enum { BSVD_F64 = 0, BSVD_F32 = 1 };
+
+/* Kernel-selection flags for batched_svd (default 0 = planner's choice). */
+enum {
+    BSVD_SVD_FORCE_WAVE = 1u << 0,  /* wavefront-resident Jacobi (Section 4 analogue) */
+    BSVD_SVD_FORCE_LDS = 1u << 1,   /* LDS-resident Jacobi (Section 5 analogue) */
+    BSVD_SVD_FORCE_BLOCK = 1u << 2, /* block Jacobi in HBM, Gram path (Section 6.1) */
+    BSVD_SVD_QR_FIRST = 1u << 3,    /* Householder QR first, then Jacobi of R (tall inputs) */
+    BSVD_SVD_NO_QR = 1u << 4        /* never run the QR pre-step */
+};
+
+/* Create a context bound to `device` (HIP ordinal) and `stream` (a hipStream_t; NULL = the null
+ * stream). The context owns its device workspace (grown on demand, freed by bsvd_destroy) and a
+ * pinned host staging buffer. Returns BSVD_OK or an error; *ctx is NULL on failure. */
+int bsvd_create(bsvd_ctx **ctx, int device, void *stream);
+
+/* Release every resource of the context (synchronises its stream first). NULL is a no-op. */
+void bsvd_destroy(bsvd_ctx *ctx);
+
+/* Text of the last error reported on this context ("" if none). Valid until the next call. */
+const char *bsvd_last_error(const bsvd_ctx *ctx);
+
+/* Block until all work enqueued by this context has finished. */
+int bsvd_sync(bsvd_ctx *ctx);
+
+/* Library version string. */
+const char *bsvd_version(void);
+
+/*
+ * batched_svd -- reduced SVD A_b = U_b diag(S_b) V_b^T of every instance by one-sided Jacobi
+ * (Section 2.2, Algorithm 2: sweeps over all column pairs; each pair's 2x2 Gram yields a plane
+ * rotation applied to the pair; singular values are the final column norms, left vectors the
+ * normalised columns, right vectors the accumulated rotations). Column pairs are visited in
+ * round-robin order, n/2 disjoint pairs at a time (Section 5). Matrices with m < n are handled
+ * through their transpose.
+ *
+ *   dtype       BSVD_F64 (or BSVD_F32: data and rotations in FP32, angles and norms in FP64)
+ *   batch       number of instances (0 is allowed and does nothing)
+ *   m, n        host int[batch], m, n >= 1
+ *   A, lda      host array of device pointers to the inputs; lda[b] >= m[b]. Not modified.
+ *   S           host array of device pointers; S[b] receives k = min(m, n) singular values,
+ *               descending (ties keep column order)
+ *   U, ldu      nullable; if given, U[b] (nullable entry) receives the m x k left vectors, ldu >= m
+ *   V, ldv      nullable; if given, V[b] (nullable entry) receives the n x k right vectors, ldv >= n
+ *   tol         convergence threshold: a pair is rotated only while |a_i . a_j| > tol ||a_i|| ||a_j||;
+ *               the iteration stops after a sweep with no rotation. <= 0 selects 1e-15 (F64) or
+ *               1e-6 (F32).
+ *   max_sweeps  sweep cap (<= 0 selects 60); reaching it sets info = 1
+ *   sweeps      nullable DEVICE int[batch]: sweeps executed (including the final check sweep)
+ *   info        nullable DEVICE int[batch]: per-instance info code
+ *   flags       BSVD_SVD_* kernel-selection flags (0 = automatic)
+ * Returns BSVD_OK, BSVD_EARG, BSVD_EUNSUP (no kernel for a shape / dtype), BSVD_ENOMEM or BSVD_EHIP.
+ */
+int batched_svd(bsvd_ctx *ctx, int dtype, int batch, const int *m, const int *n, const void *const *A,
+                const int *lda, void *const *S, void *const *U, const int *ldu, void *const *V,
+                const int *ldv, double tol, int max_sweeps, int *sweeps, int *info, unsigned flags);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BSVD_H */

@@ -1,0 +1,102 @@
+"""MI355X (gfx950) batched QR / one-sided Jacobi SVD / randomized SVD.
+
+Python entry points with the same names as the C ABI in include/bsvd.h. Torch is used for device
+memory and streams only; every numerical step runs in the HIP kernels of libbsvd.so.
+
+Layout helpers: the C ABI is column-major. ``svd(A)`` accepts a uniform batch as a torch tensor
+[b, m, n] (logical matrices) and converts it to column-major storage [b, n, m] before the call.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import BSVD_F32, BSVD_F64, BsvdError  # noqa: F401
+
+__all__ = ["batched_svd", "svd", "colmajor", "from_colmajor", "BsvdError"]
+
+
+def _dtype_code(dt):
+    if dt == torch.float64:
+        return BSVD_F64
+    if dt == torch.float32:
+        return BSVD_F32
+    raise TypeError("only float64 / float32 are supported, got %s" % dt)
+
+
+def _ctx(device):
+    dev = torch.device(device)
+    idx = dev.index if dev.index is not None else torch.cuda.current_device()
+    st = torch.cuda.current_stream(idx).cuda_stream
+    return _lib.context_for(idx, st)
+
+
+def colmajor(A: torch.Tensor) -> torch.Tensor:
+    """[b, m, n] logical batch -> [b, n, m] contiguous storage (column-major per instance)."""
+    return A.transpose(-1, -2).contiguous()
+
+
+def from_colmajor(S: torch.Tensor) -> torch.Tensor:
+    """[b, n, m] column-major storage -> [b, m, n] logical view."""
+    return S.transpose(-1, -2)
+
+
+def batched_svd(m, n, A_ptrs, lda, S_ptrs, U_ptrs=None, ldu=None, V_ptrs=None, ldv=None, *, dtype=BSVD_F64,
+                tol=0.0, max_sweeps=0, sweeps=None, info=None, flags=0, device=None):
+    """Direct mirror of the C entry point ``batched_svd`` (host shape arrays, host arrays of device
+    pointers, device int32 tensors for sweeps / info). Enqueued on torch's current stream."""
+    L = _lib.lib()
+    ctx = _ctx(device if device is not None else torch.cuda.current_device())
+    m = _lib.i32(m)
+    n = _lib.i32(n)
+    batch = len(m)
+    A_ptrs = _lib.ptrs(A_ptrs)
+    S_ptrs = _lib.ptrs(S_ptrs)
+    lda = _lib.i32(lda)
+    U_ptrs = None if U_ptrs is None else _lib.ptrs(U_ptrs)
+    V_ptrs = None if V_ptrs is None else _lib.ptrs(V_ptrs)
+    ldu = None if ldu is None else _lib.i32(ldu)
+    ldv = None if ldv is None else _lib.i32(ldv)
+    rc = L.batched_svd(ctx.h, int(dtype), batch, _lib.as_ip(m), _lib.as_ip(n), _lib.as_vp(A_ptrs), _lib.as_ip(lda),
+                       _lib.as_vp(S_ptrs), _lib.as_vp(U_ptrs), _lib.as_ip(ldu), _lib.as_vp(V_ptrs), _lib.as_ip(ldv),
+                       float(tol), int(max_sweeps), None if sweeps is None else ctypes_ptr(sweeps),
+                       None if info is None else ctypes_ptr(info), int(flags))
+    ctx.check(rc)
+
+
+def ctypes_ptr(t: torch.Tensor):
+    import ctypes
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _strided_ptrs(t: torch.Tensor, batch: int):
+    base = t.data_ptr()
+    stride = t.stride(0) * t.element_size()
+    return base + stride * np.arange(batch, dtype=np.uint64)
+
+
+def svd(A: torch.Tensor, *, want_u=True, want_v=True, tol=0.0, max_sweeps=0, flags=0):
+    """SVD of a uniform batch A [b, m, n] (float64 / float32, on a GPU).
+
+    Returns (S [b, k], U [b, m, k] | None, V [b, n, k] | None, sweeps [b], info [b]), k = min(m, n).
+    """
+    if A.dim() != 3 or not A.is_cuda:
+        raise ValueError("A must be a [b, m, n] GPU tensor")
+    b, m, n = A.shape
+    k = min(m, n)
+    dt = _dtype_code(A.dtype)
+    Acm = colmajor(A)
+    dev = A.device
+    S = torch.empty((b, k), dtype=A.dtype, device=dev)
+    Us = torch.empty((b, k, m), dtype=A.dtype, device=dev) if want_u else None
+    Vs = torch.empty((b, k, n), dtype=A.dtype, device=dev) if want_v else None
+    sweeps = torch.empty(b, dtype=torch.int32, device=dev)
+    info = torch.empty(b, dtype=torch.int32, device=dev)
+    if b == 0:
+        return S, (from_colmajor(Us) if want_u else None), (from_colmajor(Vs) if want_v else None), sweeps, info
+    batched_svd(np.full(b, m), np.full(b, n), _strided_ptrs(Acm, b), np.full(b, m), _strided_ptrs(S, b),
+                _strided_ptrs(Us, b) if want_u else None, np.full(b, m) if want_u else None,
+                _strided_ptrs(Vs, b) if want_v else None, np.full(b, n) if want_v else None,
+                dtype=dt, tol=tol, max_sweeps=max_sweeps, sweeps=sweeps, info=info, flags=flags, device=dev)
+    return S, (from_colmajor(Us) if want_u else None), (from_colmajor(Vs) if want_v else None), sweeps, info

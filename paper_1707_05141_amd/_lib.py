@@ -1,0 +1,118 @@
+"""ctypes binding of libbsvd.so: argument marshalling only.
+
+Every numerical step runs in the HIP kernels of the library. If the library has not been built this
+module raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbsvd.so")
+
+BSVD_OK, BSVD_EARG, BSVD_EHIP, BSVD_ENOMEM, BSVD_EUNSUP = 0, -1, -2, -3, -4
+BSVD_F64, BSVD_F32 = 0, 1
+
+SVD_FORCE_WAVE = 1 << 0
+SVD_FORCE_LDS = 1 << 1
+SVD_FORCE_BLOCK = 1 << 2
+SVD_QR_FIRST = 1 << 3
+SVD_NO_QR = 1 << 4
+
+_lib = None
+
+_vp = ctypes.c_void_p
+_ip = ctypes.POINTER(ctypes.c_int)
+
+
+class BsvdError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("bsvd error %d: %s" % (code, msg))
+        self.code = code
+
+
+def lib():
+    """Load libbsvd.so (raises if it is missing: there is no fallback path)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libbsvd.so is not built (run __graft_entry__.build() or paper_1707_05141_amd/build.py)")
+    L = ctypes.CDLL(LIB_PATH)
+    L.bsvd_create.argtypes = [ctypes.POINTER(_vp), ctypes.c_int, _vp]
+    L.bsvd_destroy.argtypes = [_vp]
+    L.bsvd_last_error.argtypes = [_vp]
+    L.bsvd_last_error.restype = ctypes.c_char_p
+    L.bsvd_sync.argtypes = [_vp]
+    L.bsvd_version.restype = ctypes.c_char_p
+    L.batched_svd.argtypes = [_vp, ctypes.c_int, ctypes.c_int, _ip, _ip, _vp, _ip, _vp, _vp, _ip, _vp, _ip,
+                              ctypes.c_double, ctypes.c_int, _vp, _vp, ctypes.c_uint]
+    _lib = L
+    return L
+
+
+def exported_symbols():
+    return ["bsvd_create", "bsvd_destroy", "bsvd_last_error", "bsvd_sync", "bsvd_version", "batched_svd"]
+
+
+def i32(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.int32))
+
+
+def ptrs(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.uint64))
+
+
+def as_ip(a):
+    return None if a is None else a.ctypes.data_as(_ip)
+
+
+def as_vp(a):
+    return None if a is None else ctypes.c_void_p(a.ctypes.data)
+
+
+class Context:
+    """A library context bound to one device and one HIP stream."""
+
+    def __init__(self, device: int, stream_handle: int):
+        L = lib()
+        h = _vp()
+        rc = L.bsvd_create(ctypes.byref(h), int(device), _vp(int(stream_handle) if stream_handle else None))
+        if rc != BSVD_OK:
+            raise BsvdError(rc, "bsvd_create failed")
+        self.h = h
+        self.device = device
+        self.stream = stream_handle
+
+    def check(self, rc):
+        if rc != BSVD_OK:
+            raise BsvdError(rc, lib().bsvd_last_error(self.h).decode())
+
+    def sync(self):
+        self.check(lib().bsvd_sync(self.h))
+
+    def close(self):
+        if self.h:
+            lib().bsvd_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_ctx_cache = {}
+
+
+def context_for(device: int, stream_handle: int) -> Context:
+    key = (int(device), int(stream_handle))
+    c = _ctx_cache.get(key)
+    if c is None:
+        c = Context(device, stream_handle)
+        _ctx_cache[key] = c
+    return c

@@ -1,0 +1,31 @@
+// Library context: stream, device workspace, pinned staging buffer and last error.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+namespace bsvd {
+
+struct Ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    void *dws = nullptr;  // device workspace (descriptors, lists, intermediates)
+    size_t dws_size = 0;
+    void *hws = nullptr;  // pinned host staging for descriptor uploads
+    size_t hws_size = 0;
+    hipEvent_t staged = nullptr;  // recorded after the last staging upload
+    bool staged_pending = false;
+
+    int fail(int code, const char *fmt, ...);
+    int hip_fail(hipError_t e, const char *what);
+    // Grow the device workspace to at least `bytes` (synchronises the stream when it grows).
+    int ensure_device(size_t bytes);
+    // Wait until the staging buffer is free again and grow it to at least `bytes`.
+    int ensure_host(size_t bytes);
+    // Copy the first `bytes` of the staging buffer to the start of the device workspace.
+    int upload(size_t bytes);
+};
+
+}  // namespace bsvd

@@ -1,0 +1,40 @@
+// Device helpers for the one-sided Jacobi kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace bsvd {
+
+// rot(G) of Algorithm 2 for the 2x2 Gram [[ai, g], [g, aj]] of columns (w_i, w_j), i < j:
+// returns (c, s) such that w_i' = c w_i - s w_j and w_j' = s w_i + c w_j are orthogonal in exact
+// arithmetic. Rutishauser's small-angle form t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)),
+// zeta = (aj - ai) / (2 g), multiplied through by |2 g| so that one division suffices.
+__device__ __forceinline__ void jacobi_rot(double ai, double aj, double g, double &c, double &s) {
+    double d = aj - ai;
+    double tg = 2.0 * g;
+    double den = fabs(d) + sqrt(d * d + tg * tg);
+    double t = (d >= 0.0 ? tg : -tg) / den;
+    c = rsqrt(1.0 + t * t);
+    s = c * t;
+}
+
+// Round-robin ("circle") schedule for NP (even) columns: at step s in [0, NP-1) column NP-1 meets
+// column s and every other column p meets (2s - p) mod (NP-1). Each step is a perfect matching and
+// the NP-1 steps of a sweep visit every pair exactly once (Section 5 visits pairs in round-robin
+// order, NP/2 disjoint pairs per step).
+__device__ __forceinline__ int rr_partner(int p, int s, int NP) {
+    const int L = NP - 1;
+    if (p == L) return s;
+    if (p == s) return L;
+    int q = 2 * s - p;
+    q %= L;
+    if (q < 0) q += L;
+    return q;
+}
+
+template <typename T>
+__device__ __forceinline__ T shfl_any(T v, int src) {
+    return __shfl(v, src, 64);
+}
+
+}  // namespace bsvd

@@ -1,0 +1,206 @@
+// Wavefront-resident one-sided Jacobi SVD (register kernel of Section 4, re-designed for wave64).
+//
+// The paper keeps one matrix row per thread and visits column pairs serially, paying for the
+// cross-lane dot-product reductions and for a rotation computed redundantly by every thread of the
+// warp (Section 4.2 profiles that redundant part as the dominant cost). Here one LANE owns one
+// COLUMN of the working matrix and the matching column of V, both in VGPRs (gfx950 gives a lane up
+// to 512 registers, so a 64 x 32 FP64 matrix with its V fits in one wave). Each round-robin step
+// pairs every column with a partner lane (NP/2 disjoint pairs, Section 5): the partner's column is
+// fetched with cross-lane permutes, the three dot products of the 2x2 Gram are lane-local serial
+// sums (no reduction tree), both lanes of the pair derive the same rotation from bit-identical
+// inputs, and each lane rotates only its own column. With NP columns, 64/NP matrices share a wave.
+//
+// Precision: T = double, or T = float with the dot products, norms, rotation angle and convergence
+// test in double and the rotation applied in float.
+
+#include "common.hpp"
+#include "jacobi_device.hpp"
+
+namespace bsvd {
+
+template <typename T, int MMAX, int NP>
+__global__ __launch_bounds__(64) void jacobi_wave_kernel(const SvdDesc *__restrict__ descs,
+                                                         const int *__restrict__ list, int count, double tol,
+                                                         int max_sweeps, int *__restrict__ sweeps_out,
+                                                         int *__restrict__ info_out) {
+    constexpr int G = 64 / NP;
+    const int lane = threadIdx.x;
+    const int grp = lane / NP;
+    const int p = lane - grp * NP;
+    const int base = grp * NP;
+    const unsigned long long gmask = (NP == 64) ? ~0ull : (((1ull << NP) - 1ull) << base);
+    const int item = blockIdx.x * G + grp;
+    const bool active = item < count;
+
+    int inst = -1;
+    SvdDesc D;
+    D.A = nullptr; D.S = nullptr; D.U = nullptr; D.V = nullptr;
+    D.m = D.n = D.lda = D.ldu = D.ldv = D.trans = D.M = D.N = 0;
+    if (active) {
+        inst = list[item];
+        D = descs[inst];
+    }
+    const bool col_ok = active && p < D.N;
+
+    T a[MMAX];
+    T v[NP];
+    bool finite = true;
+    const T *Ap = static_cast<const T *>(D.A);
+#pragma unroll
+    for (int r = 0; r < MMAX; ++r) {
+        T x = T(0);
+        if (col_ok && r < D.M) x = D.trans ? Ap[p + (size_t)r * D.lda] : Ap[r + (size_t)p * D.lda];
+        finite = finite && __builtin_isfinite(x);
+        a[r] = x;
+    }
+#pragma unroll
+    for (int r = 0; r < NP; ++r) v[r] = (col_ok && r == p) ? T(1) : T(0);
+
+    const bool bad = (__ballot(!finite) & gmask) != 0ull;
+    bool done = bad || !active;
+    int sweeps = 0;
+    bool converged = false;
+
+    for (int sw = 0; sw < max_sweeps; ++sw) {
+        if (__ballot(!done) == 0ull) break;  // every matrix of the wave has converged
+        bool rotated = false;
+        for (int s = 0; s < NP - 1; ++s) {
+            const int q = rr_partner(p, s, NP);
+            const int src = base + q;
+            T pa[MMAX];
+            double alpha = 0.0, gam = 0.0;
+#pragma unroll
+            for (int r = 0; r < MMAX; ++r) {
+                pa[r] = shfl_any(a[r], src);
+                alpha = fma((double)a[r], (double)a[r], alpha);
+                gam = fma((double)a[r], (double)pa[r], gam);
+            }
+            const double beta = shfl_any(alpha, src);
+            const double ai = p < q ? alpha : beta;
+            const double aj = p < q ? beta : alpha;
+            const bool rot = !done && ai > 0.0 && aj > 0.0 && fabs(gam) > tol * sqrt(ai * aj);
+            if (__ballot(rot) != 0ull) {
+                double c = 1.0, sn = 0.0;
+                if (rot) jacobi_rot(ai, aj, gam, c, sn);
+                // i-lane (p < q): w_i' = c w_i - s w_j ; j-lane: w_j' = s w_i + c w_j
+                const T cc = rot ? (T)c : T(1);
+                const T ss = rot ? (T)(p < q ? -sn : sn) : T(0);
+#pragma unroll
+                for (int r = 0; r < MMAX; ++r) a[r] = cc * a[r] + ss * pa[r];
+#pragma unroll
+                for (int r = 0; r < NP; ++r) {
+                    const T pv = shfl_any(v[r], src);
+                    v[r] = cc * v[r] + ss * pv;
+                }
+                rotated = rotated || rot;
+            }
+        }
+        const unsigned long long rb = __ballot(rotated);
+        if (!done) {
+            sweeps = sw + 1;
+            if ((rb & gmask) == 0ull) {
+                done = true;
+                converged = true;
+            }
+        }
+    }
+
+    // Singular values = column norms; rank of each column within its matrix by descending norm,
+    // ties broken by column index (stable).
+    double nrm2 = 0.0;
+#pragma unroll
+    for (int r = 0; r < MMAX; ++r) nrm2 = fma((double)a[r], (double)a[r], nrm2);
+    const double sig = sqrt(nrm2);
+    int rank = 0;
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+        const double sq = shfl_any(sig, base + q);
+        rank += (sq > sig || (sq == sig && q < p)) ? 1 : 0;
+    }
+    if (!active) return;
+
+    T *S = static_cast<T *>(D.S);
+    if (bad) {
+        if (p < D.N) S[p] = (T)__builtin_nan("");
+    } else if (col_ok) {
+        S[rank] = (T)sig;
+        T *L = static_cast<T *>(D.trans ? D.V : D.U);
+        const int ldl = D.trans ? D.ldv : D.ldu;
+        T *R = static_cast<T *>(D.trans ? D.U : D.V);
+        const int ldr = D.trans ? D.ldu : D.ldv;
+        if (L) {
+            const double inv = sig > 0.0 ? 1.0 / sig : 0.0;
+#pragma unroll
+            for (int r = 0; r < MMAX; ++r)
+                if (r < D.M) L[r + (size_t)rank * ldl] = (T)((double)a[r] * inv);
+        }
+        if (R) {
+#pragma unroll
+            for (int r = 0; r < NP; ++r)
+                if (r < D.N) R[r + (size_t)rank * ldr] = v[r];
+        }
+    }
+    if (p == 0) {
+        if (info_out) info_out[inst] = bad ? INFO_NONFINITE : (converged ? INFO_OK : INFO_SWEEPS);
+        if (sweeps_out) sweeps_out[inst] = bad ? 0 : sweeps;
+    }
+}
+
+template <typename T, int MMAX, int NP>
+static hipError_t launch_one(const SvdDesc *d, const int *list, int count, double tol, int max_sweeps, int *sw,
+                             int *info, hipStream_t st) {
+    constexpr int G = 64 / NP;
+    const int blocks = (count + G - 1) / G;
+    hipLaunchKernelGGL((jacobi_wave_kernel<T, MMAX, NP>), dim3(blocks), dim3(64), 0, st, d, list, count, tol,
+                       max_sweeps, sw, info);
+    return hipGetLastError();
+}
+
+static int pow2_at_least(int x) {
+    int p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+bool jacobi_wave_supported(int dtype, int M, int N, int *mmax, int *np) {
+    (void)dtype;
+    const int NPv = pow2_at_least(N < 2 ? 2 : N);
+    const int Mv = pow2_at_least(M < NPv ? NPv : M);
+    if (NPv > 32 || Mv > 64) return false;
+    if (mmax) *mmax = Mv;
+    if (np) *np = NPv;
+    return true;
+}
+
+#define BSVD_WAVE_CASE(MM, NN)                                                                   \
+    if (mmax == MM && np == NN)                                                                  \
+        return dtype == 0 ? launch_one<double, MM, NN>(d, list, count, tol, max_sweeps, sweeps, info, st) \
+                          : launch_one<float, MM, NN>(d, list, count, tol, max_sweeps, sweeps, info, st);
+
+hipError_t launch_jacobi_wave(int dtype, int mmax, int np, const SvdDesc *d, const int *list, int count,
+                              double tol, int max_sweeps, int *sweeps, int *info, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    BSVD_WAVE_CASE(2, 2)
+    BSVD_WAVE_CASE(4, 2)
+    BSVD_WAVE_CASE(8, 2)
+    BSVD_WAVE_CASE(16, 2)
+    BSVD_WAVE_CASE(32, 2)
+    BSVD_WAVE_CASE(64, 2)
+    BSVD_WAVE_CASE(4, 4)
+    BSVD_WAVE_CASE(8, 4)
+    BSVD_WAVE_CASE(16, 4)
+    BSVD_WAVE_CASE(32, 4)
+    BSVD_WAVE_CASE(64, 4)
+    BSVD_WAVE_CASE(8, 8)
+    BSVD_WAVE_CASE(16, 8)
+    BSVD_WAVE_CASE(32, 8)
+    BSVD_WAVE_CASE(64, 8)
+    BSVD_WAVE_CASE(16, 16)
+    BSVD_WAVE_CASE(32, 16)
+    BSVD_WAVE_CASE(64, 16)
+    BSVD_WAVE_CASE(32, 32)
+    BSVD_WAVE_CASE(64, 32)
+    return hipErrorInvalidValue;
+}
+
+}  // namespace bsvd

@@ -1,0 +1,51 @@
+"""Comparison helpers for GPU results against the oracle (numpy, host side)."""
+import numpy as np
+
+U64 = np.finfo(np.float64).eps
+
+
+def sign_fix(X):
+    """Flip each column so that its largest-magnitude entry is positive."""
+    idx = np.argmax(np.abs(X), axis=0)
+    s = np.sign(X[idx, np.arange(X.shape[1])])
+    s[s == 0] = 1.0
+    return X * s[None, :]
+
+
+def separated(S, rel_gap):
+    """Mask of singular values whose distance to both neighbours exceeds rel_gap * sigma_max."""
+    k = len(S)
+    if k == 0:
+        return np.zeros(0, bool)
+    smax = max(S[0], 1e-300)
+    g = np.full(k, np.inf)
+    if k > 1:
+        d = np.abs(np.diff(S))
+        g[:-1] = np.minimum(g[:-1], d)
+        g[1:] = np.minimum(g[1:], d)
+    return (g > rel_gap * smax) & (S > rel_gap * smax)
+
+
+def check_svd(A, S, U, V, S_ref, U_ref, V_ref, sig_tol, vec_gap=1e-6, vec_tol=1e-9, fac_tol=None):
+    """Singular values within sig_tol * sigma_max; invariants; sign-fixed vectors of well-separated
+    singular values element by element."""
+    m, n = A.shape
+    k = min(m, n)
+    smax = max(S_ref[0], 1e-300) if k else 1.0
+    assert S.shape == (k,)
+    err = np.max(np.abs(S - S_ref)) if k else 0.0
+    assert err <= sig_tol * smax, "sigma error %.3e > %.1e sigma_max" % (err / smax, sig_tol)
+    assert np.all(np.diff(S) <= 0), "sigma not descending"
+    if fac_tol is None:
+        fac_tol = 50 * max(m, n) * U64
+    nA = np.linalg.norm(A)
+    if U is not None and V is not None:
+        R = A - (U * S[None, :]) @ V.T
+        assert np.linalg.norm(R) <= fac_tol * max(nA, 1e-300), "reconstruction %.3e" % (np.linalg.norm(R) / nA)
+    if V is not None:
+        assert np.linalg.norm(V.T @ V - np.eye(k)) <= fac_tol * k
+    good = separated(S_ref, vec_gap)
+    if U is not None and U_ref is not None and good.any():
+        np.testing.assert_allclose(sign_fix(U[:, good]), sign_fix(U_ref[:, good]), rtol=0, atol=vec_tol)
+    if V is not None and V_ref is not None and good.any():
+        np.testing.assert_allclose(sign_fix(V[:, good]), sign_fix(V_ref[:, good]), rtol=0, atol=vec_tol)

@@ -1,0 +1,49 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports every entry point that
+include/bsvd.h declares, and rejects bad batch-level arguments without launching anything."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1707_05141_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADERS = [os.path.join(ROOT, "include", f) for f in os.listdir(os.path.join(ROOT, "include")) if f.endswith(".h")]
+
+
+def _declared_functions():
+    names = []
+    for h in HEADERS:
+        txt = open(h).read()
+        txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+        for mt in re.finditer(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_ \*]*?\b([A-Za-z_][A-Za-z0-9_]*)\s*\(", txt, re.M):
+            name = mt.group(1)
+            if name not in ("if", "while", "for", "return", "sizeof"):
+                names.append(name)
+    return sorted(set(names))
+
+
+def test_header_declares_entry_points():
+    names = _declared_functions()
+    for required in ("batched_svd", "bsvd_create", "bsvd_destroy", "bsvd_last_error"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("libbsvd.so not built")
+    L = ctypes.CDLL(_lib.LIB_PATH)
+    missing = [n for n in _declared_functions() if not hasattr(L, n)]
+    assert not missing, missing
+    L.bsvd_version.restype = ctypes.c_char_p
+    assert b"gfx950" in L.bsvd_version()
+
+
+def test_null_context_is_rejected():
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("libbsvd.so not built")
+    L = _lib.lib()
+    rc = L.batched_svd(None, 0, 1, None, None, None, None, None, None, None, None, None, 0.0, 0, None, None, 0)
+    assert rc == _lib.BSVD_EARG
+    assert L.bsvd_last_error(None) == b"null context"

@@ -1,0 +1,114 @@
+"""GPU parity of batched_svd (one-sided Jacobi) against the FP64 oracle, through the C ABI."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1707_05141_amd import synth
+from svd_checks import check_svd
+
+pytestmark = pytest.mark.gpu
+
+import paper_1707_05141_amd as P  # noqa: E402
+from paper_1707_05141_amd import _lib  # noqa: E402
+
+
+def _run(A_np, dtype=torch.float64, **kw):
+    A = torch.from_numpy(A_np).to(device="cuda", dtype=dtype)
+    S, U, V, sw, info = P.svd(A, **kw)
+    torch.cuda.synchronize()
+    return (S.double().cpu().numpy(), None if U is None else U.double().cpu().numpy(),
+            None if V is None else V.double().cpu().numpy(), sw.cpu().numpy(), info.cpu().numpy())
+
+
+def _compare_batch(A, S, U, V, info, sig_tol=1e-12, vec_tol=1e-9, fac_tol=None):
+    So, Uo, Vo, swo, info_o = oracle.batched_jacobi_svd(A)
+    for b in range(A.shape[0]):
+        assert info[b] == 0, (b, info[b])
+        check_svd(A[b], S[b], U[b], V[b], So[b], Uo[b], Vo[b], sig_tol, vec_tol=vec_tol, fac_tol=fac_tol)
+    return swo
+
+
+def test_wave_gaussian_32x32_full_batch():
+    """1,000 Gaussian 32 x 32 matrices, FP64, tol 1e-15: every instance against the oracle."""
+    print("case: wave 1000 x 32x32 f64", flush=True)
+    A = synth.batch_gaussian(1000, 32, 32, seed=1)
+    S, U, V, sw, info = _run(A)
+    swo = _compare_batch(A, S, U, V, info)
+    assert np.all(sw >= 2) and np.all(sw <= 30)
+    print("gpu sweeps mean %.2f, oracle mean %.2f" % (sw.mean(), swo.mean()))
+
+
+@pytest.mark.parametrize("m,n,b", [(1, 1, 3), (2, 2, 5), (5, 3, 7), (3, 5, 7), (17, 13, 9), (13, 17, 9),
+                                   (33, 31, 3), (64, 32, 5), (32, 64, 5), (64, 20, 6), (48, 24, 11), (64, 2, 33),
+                                   (7, 1, 4), (1, 7, 4), (32, 32, 1), (31, 31, 3)])
+def test_wave_shapes_ragged(m, n, b):
+    print("case: wave %dx%d batch %d" % (m, n, b), flush=True)
+    A = synth.batch_gaussian(b, m, n, seed=m * 1000 + n)
+    S, U, V, sw, info = _run(A)
+    _compare_batch(A, S, U, V, info)
+
+
+@pytest.mark.parametrize("m,n", [(32, 32), (64, 32), (24, 24)])
+def test_wave_graded_spectrum(m, n):
+    """Prescribed spectrum sigma_i = 10^(-8(i-1)/(n-1)): singular values to 1e-12 sigma_max."""
+    print("case: wave graded %dx%d" % (m, n), flush=True)
+    k = min(m, n)
+    sig = synth.graded_sigma_log(k, 8.0)
+    A = np.stack([synth.prescribed(m, n, sig, seed=3, inst=i) for i in range(20)])
+    S, U, V, sw, info = _run(A)
+    assert np.all(info == 0)
+    for b in range(20):
+        assert np.max(np.abs(S[b] - sig)) <= 1e-12
+    _compare_batch(A, S, U, V, info, vec_tol=1e-7)
+
+
+def test_wave_fp32_variant():
+    print("case: wave f32 32x32", flush=True)
+    A = synth.batch_gaussian(64, 32, 32, seed=5)
+    A32 = A.astype(np.float32).astype(np.float64)  # the input the FP32 path actually sees
+    S, U, V, sw, info = _run(A, dtype=torch.float32)
+    So, Uo, Vo, swo, io = oracle.batched_jacobi_svd(A32)
+    assert np.all(info == 0)
+    for b in range(64):
+        assert np.max(np.abs(S[b] - So[b])) <= 1e-5 * So[b][0]
+        R = A32[b] - (U[b] * S[b][None, :]) @ V[b].T
+        assert np.linalg.norm(R) <= 1e-5 * np.linalg.norm(A32[b])
+
+
+def test_wave_no_vectors_and_empty_batch():
+    A = synth.batch_gaussian(10, 16, 16, seed=2)
+    S, U, V, sw, info = _run(A, want_u=False, want_v=False)
+    So = oracle.batched_jacobi_svd(A)[0]
+    assert U is None and V is None
+    np.testing.assert_allclose(S, So, atol=1e-12 * So.max())
+    S0, U0, V0, sw0, info0 = P.svd(torch.zeros((0, 8, 8), dtype=torch.float64, device="cuda"))
+    assert S0.shape == (0, 8)
+
+
+def test_wave_nonfinite_and_sweep_cap():
+    A = synth.batch_gaussian(4, 16, 16, seed=9)
+    A[1, 3, 4] = np.nan
+    S, U, V, sw, info = _run(A)
+    assert info[1] == 3 and np.all(np.isnan(S[1]))
+    assert info[0] == 0 and info[2] == 0 and info[3] == 0
+    S, U, V, sw, info = _run(synth.batch_gaussian(4, 16, 16, seed=9), max_sweeps=1)
+    assert np.all(info == 1) and np.all(sw == 1)
+
+
+def test_wave_bitwise_reproducible():
+    A = synth.batch_gaussian(200, 32, 32, seed=7)
+    r1 = _run(A)
+    r2 = _run(A)
+    for x, y in zip(r1, r2):
+        np.testing.assert_array_equal(x, y)
+
+
+def test_bad_arguments_rejected():
+    A = torch.zeros((2, 8, 8), dtype=torch.float64, device="cuda")
+    S = torch.zeros((2, 8), dtype=torch.float64, device="cuda")
+    with pytest.raises(P.BsvdError) as e:
+        P.batched_svd([8, 8], [8, 8], [A.data_ptr(), A.data_ptr()], [8, 4], [S.data_ptr(), S.data_ptr()])
+    assert e.value.code == _lib.BSVD_EARG
+    with pytest.raises(P.BsvdError):
+        P.batched_svd([8, 0], [8, 8], [A.data_ptr(), A.data_ptr()], [8, 8], [S.data_ptr(), S.data_ptr()])
