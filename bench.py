@@ -109,7 +109,69 @@ def cpu_baseline_jacobi(A_np, oracle):
                 sample="full batch of %d instances, best of %d runs (%.1f s CPU wall total)" % (b, reps, t_total))
 
 
-WORKLOADS = {"c1": run_c1}
+def run_c2(args, torch, P, synth):
+    """10,000 graded 64 x 64 plus 20,000 graded 128 x 32 (sigma_i = 10^(-8(i-1)/(n-1))): Householder
+    QR, one-sided Jacobi of R (rows), U = Q U_R; one call per shape group, both in a step."""
+    import oracle
+    from paper_1707_05141_amd import _lib
+    groups = []
+    for (b, m, n) in [(10000, 64, 64), (20000, 128, 32)]:
+        A_np = synth.batch_prescribed(b, m, n, synth.graded_sigma_log(n, 8.0), seed=2)
+        A = torch.from_numpy(A_np).cuda()
+        k = min(m, n)
+        Acm = P.colmajor(A)
+        S = torch.empty((b, k), dtype=A.dtype, device="cuda")
+        U = torch.empty((b, k, m), dtype=A.dtype, device="cuda")
+        V = torch.empty((b, k, n), dtype=A.dtype, device="cuda")
+        sw = torch.empty(b, dtype=torch.int32, device="cuda")
+        info = torch.empty(b, dtype=torch.int32, device="cuda")
+        ptr = lambda t, b=b: t.data_ptr() + t.stride(0) * t.element_size() * np.arange(b, dtype=np.uint64)
+        groups.append(dict(A_np=A_np, A=A, Acm=Acm, S=S, U=U, V=V, sw=sw, info=info, m=m, n=n, b=b,
+                           args=(np.full(b, m), np.full(b, n), ptr(Acm), np.full(b, m), ptr(S), ptr(U), np.full(b, m),
+                                 ptr(V), np.full(b, n))))
+
+    def step():
+        for g in groups:
+            P.batched_svd(*g["args"], sweeps=g["sw"], info=g["info"], flags=_lib.SVD_QR_FIRST)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ev[i][0].record()
+        step()
+        ev[i][1].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    step_ms = float(np.mean([s.elapsed_time(e) for s, e in ev]))
+    flops = 0.0
+    errs = []
+    for g in groups:
+        assert int(g["info"].max().item()) == 0
+        sw = g["sw"].cpu().numpy()
+        m, n = g["m"], g["n"]
+        qr_fl = 2 * (2 * m * n * n - 2 * n ** 3 / 3)  # factorisation + thin Q
+        flops += g["b"] * qr_fl + jacobi_model_flops(n, n, sw) + g["b"] * 2 * m * n * n
+        sig = synth.graded_sigma_log(n, 8.0)
+        errs.append(float(np.max(np.abs(g["S"].cpu().numpy() - sig[None, :]))))
+    assert max(errs) <= 1e-12, errs
+    total = sum(g["b"] for g in groups)
+    ms_per_step = wall * 1e3 / args.steps
+    achieved = flops / (step_ms * 1e-3) / 1e12
+    res = dict(value=total / (ms_per_step * 1e-3), unit="SVDs/s", ms_per_step=ms_per_step, dtype="f64",
+               config=dict(workload="qr_jacobi_f64_10000x64x64_20000x128x32", batch=total, kappa=1e8,
+                           mean_sweeps={"%dx%d" % (g["m"], g["n"]): float(g["sw"].float().mean().item()) for g in groups},
+                           gflops_model=flops / 1e9, gflop_per_s=flops / (ms_per_step * 1e-3) / 1e9,
+                           max_sigma_err=max(errs)),
+               roofline=dict(bound="alu", achieved=achieved, peak=FP64_PEAK_TFLOPS, unit="TFLOP/s",
+                             frac=achieved / FP64_PEAK_TFLOPS, traffic=None, kernel="whole step (QR + Jacobi + GEMM)",
+                             kernel_ms=step_ms))
+    return res
+
+
+WORKLOADS = {"c1": run_c1, "c2": run_c2}
 
 
 def main():

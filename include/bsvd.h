@@ -47,8 +47,9 @@ enum {
     BSVD_SVD_FORCE_WAVE = 1u << 0,  /* wavefront-resident Jacobi (Section 4 analogue) */
     BSVD_SVD_FORCE_LDS = 1u << 1,   /* LDS-resident Jacobi (Section 5 analogue) */
     BSVD_SVD_FORCE_BLOCK = 1u << 2, /* block Jacobi in HBM, Gram path (Section 6.1) */
-    BSVD_SVD_QR_FIRST = 1u << 3,    /* Householder QR first, then Jacobi of R (tall inputs) */
-    BSVD_SVD_NO_QR = 1u << 4        /* never run the QR pre-step */
+    BSVD_SVD_QR_FIRST = 1u << 3,    /* Householder QR first, then Jacobi of R (also for square inputs) */
+    BSVD_SVD_NO_QR = 1u << 4,       /* never run the QR pre-step (default: QR first when m != n) */
+    BSVD_SVD_JACOBI_ON_R = 1u << 5  /* after QR, rotate the columns of R instead of its rows */
 };
 
 /* Create a context bound to `device` (HIP ordinal) and `stream` (a hipStream_t; NULL = the null
@@ -74,7 +75,11 @@ const char *bsvd_version(void);
  * rotation applied to the pair; singular values are the final column norms, left vectors the
  * normalised columns, right vectors the accumulated rotations). Column pairs are visited in
  * round-robin order, n/2 disjoint pairs at a time (Section 5). Matrices with m < n are handled
- * through their transpose.
+ * through their transpose. Rectangular inputs (and square ones with BSVD_SVD_QR_FIRST) are first
+ * reduced by Householder QR (Section 2.1), W = Q R; the SVD of the min(m,n) x min(m,n) triangle R is
+ * then computed by one-sided Jacobi applied to the columns of R^T (the rows of R), which converges
+ * in far fewer sweeps than on R itself (the QR preprocessing that Section 6.3 names as a remedy for
+ * slow block-Jacobi convergence), and U = Q U_R.
  *
  *   dtype       BSVD_F64 (or BSVD_F32: data and rotations in FP32, angles and norms in FP64)
  *   batch       number of instances (0 is allowed and does nothing)
@@ -96,6 +101,24 @@ const char *bsvd_version(void);
 int batched_svd(bsvd_ctx *ctx, int dtype, int batch, const int *m, const int *n, const void *const *A,
                 const int *lda, void *const *S, void *const *U, const int *ldu, void *const *V,
                 const int *ldv, double tol, int max_sweeps, int *sweeps, int *info, unsigned flags);
+
+/*
+ * batched_qr -- Householder QR A_b = Q_b R_b of every instance (Section 2.1, Algorithm 1: one
+ * reflector per column applied to the trailing columns, reflectors accumulated into Q).
+ *
+ *   dtype       BSVD_F64 or BSVD_F32
+ *   batch       number of instances (0 does nothing)
+ *   m, n        host int[batch]; currently 1 <= m <= 512, 1 <= n <= 64
+ *   A, lda      host array of device pointers to the inputs, lda >= m. Not modified.
+ *   Q, ldq      nullable; Q[b] (nullable entry) receives the thin m x k factor, k = min(m, n),
+ *               with orthonormal columns; ldq >= m
+ *   R, ldr      nullable; R[b] (nullable entry) receives the k x n upper trapezoidal factor with
+ *               exact zeros below the diagonal; ldr >= k. The diagonal may be negative
+ *               (reflector sign beta = -sign(alpha) ||x||, sign(0) = +1).
+ * Returns BSVD_OK, BSVD_EARG, BSVD_EUNSUP (shape beyond the kernel limits), BSVD_ENOMEM or BSVD_EHIP.
+ */
+int batched_qr(bsvd_ctx *ctx, int dtype, int batch, const int *m, const int *n, const void *const *A,
+               const int *lda, void *const *Q, const int *ldq, void *const *R, const int *ldr);
 
 #ifdef __cplusplus
 }

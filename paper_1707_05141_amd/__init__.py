@@ -14,7 +14,7 @@ import torch
 from . import _lib
 from ._lib import BSVD_F32, BSVD_F64, BsvdError  # noqa: F401
 
-__all__ = ["batched_svd", "svd", "colmajor", "from_colmajor", "BsvdError"]
+__all__ = ["batched_svd", "batched_qr", "svd", "qr", "colmajor", "from_colmajor", "BsvdError"]
 
 
 def _dtype_code(dt):
@@ -65,6 +65,24 @@ def batched_svd(m, n, A_ptrs, lda, S_ptrs, U_ptrs=None, ldu=None, V_ptrs=None, l
     ctx.check(rc)
 
 
+def batched_qr(m, n, A_ptrs, lda, Q_ptrs=None, ldq=None, R_ptrs=None, ldr=None, *, dtype=BSVD_F64, device=None):
+    """Direct mirror of the C entry point ``batched_qr``. Enqueued on torch's current stream."""
+    L = _lib.lib()
+    ctx = _ctx(device if device is not None else torch.cuda.current_device())
+    m = _lib.i32(m)
+    n = _lib.i32(n)
+    batch = len(m)
+    A_ptrs = _lib.ptrs(A_ptrs)
+    lda = _lib.i32(lda)
+    Q_ptrs = None if Q_ptrs is None else _lib.ptrs(Q_ptrs)
+    R_ptrs = None if R_ptrs is None else _lib.ptrs(R_ptrs)
+    ldq = None if ldq is None else _lib.i32(ldq)
+    ldr = None if ldr is None else _lib.i32(ldr)
+    rc = L.batched_qr(ctx.h, int(dtype), batch, _lib.as_ip(m), _lib.as_ip(n), _lib.as_vp(A_ptrs), _lib.as_ip(lda),
+                      _lib.as_vp(Q_ptrs), _lib.as_ip(ldq), _lib.as_vp(R_ptrs), _lib.as_ip(ldr))
+    ctx.check(rc)
+
+
 def ctypes_ptr(t: torch.Tensor):
     import ctypes
     return ctypes.c_void_p(t.data_ptr())
@@ -100,3 +118,21 @@ def svd(A: torch.Tensor, *, want_u=True, want_v=True, tol=0.0, max_sweeps=0, fla
                 _strided_ptrs(Vs, b) if want_v else None, np.full(b, n) if want_v else None,
                 dtype=dt, tol=tol, max_sweeps=max_sweeps, sweeps=sweeps, info=info, flags=flags, device=dev)
     return S, (from_colmajor(Us) if want_u else None), (from_colmajor(Vs) if want_v else None), sweeps, info
+
+
+def qr(A: torch.Tensor, *, want_q=True, want_r=True):
+    """Householder QR of a uniform batch A [b, m, n]. Returns (Q [b, m, k] | None, R [b, k, n] | None)."""
+    if A.dim() != 3 or not A.is_cuda:
+        raise ValueError("A must be a [b, m, n] GPU tensor")
+    b, m, n = A.shape
+    k = min(m, n)
+    dt = _dtype_code(A.dtype)
+    Acm = colmajor(A)
+    Qs = torch.empty((b, k, m), dtype=A.dtype, device=A.device) if want_q else None
+    Rs = torch.empty((b, n, k), dtype=A.dtype, device=A.device) if want_r else None
+    if b > 0:
+        batched_qr(np.full(b, m), np.full(b, n), _strided_ptrs(Acm, b), np.full(b, m),
+                   _strided_ptrs(Qs, b) if want_q else None, np.full(b, m) if want_q else None,
+                   _strided_ptrs(Rs, b) if want_r else None, np.full(b, k) if want_r else None,
+                   dtype=dt, device=A.device)
+    return (from_colmajor(Qs) if want_q else None), (from_colmajor(Rs) if want_r else None)

@@ -21,6 +21,7 @@ SVD_FORCE_LDS = 1 << 1
 SVD_FORCE_BLOCK = 1 << 2
 SVD_QR_FIRST = 1 << 3
 SVD_NO_QR = 1 << 4
+SVD_JACOBI_ON_R = 1 << 5
 
 _lib = None
 
@@ -50,12 +51,14 @@ def lib():
     L.bsvd_version.restype = ctypes.c_char_p
     L.batched_svd.argtypes = [_vp, ctypes.c_int, ctypes.c_int, _ip, _ip, _vp, _ip, _vp, _vp, _ip, _vp, _ip,
                               ctypes.c_double, ctypes.c_int, _vp, _vp, ctypes.c_uint]
+    L.batched_qr.argtypes = [_vp, ctypes.c_int, ctypes.c_int, _ip, _ip, _vp, _ip, _vp, _ip, _vp, _ip]
     _lib = L
     return L
 
 
 def exported_symbols():
-    return ["bsvd_create", "bsvd_destroy", "bsvd_last_error", "bsvd_sync", "bsvd_version", "batched_svd"]
+    return ["bsvd_create", "bsvd_destroy", "bsvd_last_error", "bsvd_sync", "bsvd_version", "batched_svd",
+            "batched_qr"]
 
 
 def i32(a):

@@ -15,6 +15,64 @@
 
 using namespace bsvd;
 
+namespace {
+
+// Bump allocator for laying out one call's workspace (256-byte aligned blocks).
+struct Arena {
+    size_t off = 0;
+    size_t alloc(size_t bytes, size_t align = 256) {
+        off = (off + align - 1) & ~(align - 1);
+        const size_t r = off;
+        off += bytes;
+        return r;
+    }
+};
+
+enum { JK_WAVE = 0, JK_LDS = 1 };
+
+struct JKey {
+    int kind = 0, a = 0, b = 0;
+    bool operator<(const JKey &o) const {
+        if (kind != o.kind) return kind < o.kind;
+        if (a != o.a) return a < o.a;
+        return b < o.b;
+    }
+};
+
+struct QKey {
+    int nb = 0, seg = 0, kr = 0;
+    bool operator<(const QKey &o) const {
+        if (nb != o.nb) return nb < o.nb;
+        if (seg != o.seg) return seg < o.seg;
+        return kr < o.kr;
+    }
+};
+
+// Kernel choice for an M x N working matrix (M >= N): the wavefront-resident kernel when the
+// matrix and its V fit one wave's registers, else the LDS-resident kernel.
+int choose_jacobi(int dtype, int M, int N, unsigned flags, JKey *key) {
+    int a = 0, b = 0;
+    const bool wave_ok = jacobi_wave_supported(dtype, M, N, &a, &b);
+    int la = 0, lb = 0;
+    const bool lds_ok = jacobi_lds_supported(dtype, M, N, &la, &lb);
+    if (flags & BSVD_SVD_FORCE_WAVE) {
+        if (!wave_ok) return BSVD_EUNSUP;
+        *key = JKey{JK_WAVE, a, b};
+    } else if (flags & BSVD_SVD_FORCE_LDS) {
+        if (!lds_ok) return BSVD_EUNSUP;
+        *key = JKey{JK_LDS, la, lb};
+    } else if (wave_ok) {
+        *key = JKey{JK_WAVE, a, b};
+    } else if (lds_ok) {
+        *key = JKey{JK_LDS, la, lb};
+    } else {
+        return BSVD_EUNSUP;
+    }
+    return BSVD_OK;
+}
+
+}  // namespace
+
 namespace bsvd {
 
 int Ctx::fail(int code, const char *fmt, ...) {
@@ -138,13 +196,22 @@ int batched_svd(bsvd_ctx *ctx, int dtype, int batch, const int *m, const int *n,
     if (!m || !n || !A || !lda || !S) return c->fail(BSVD_EARG, "m, n, A, lda and S must be non-NULL");
     if (U && !ldu) return c->fail(BSVD_EARG, "U given without ldu");
     if (V && !ldv) return c->fail(BSVD_EARG, "V given without ldv");
+    if ((flags & BSVD_SVD_FORCE_WAVE) && (flags & BSVD_SVD_FORCE_LDS))
+        return c->fail(BSVD_EARG, "FORCE_WAVE and FORCE_LDS are exclusive");
+    if ((flags & BSVD_SVD_QR_FIRST) && (flags & BSVD_SVD_NO_QR))
+        return c->fail(BSVD_EARG, "QR_FIRST and NO_QR are exclusive");
+    if (flags & BSVD_SVD_FORCE_BLOCK) return c->fail(BSVD_EUNSUP, "block Jacobi path is not available");
     if (tol <= 0.0) tol = (dtype == BSVD_F64) ? 1e-15 : 1e-6;
     if (max_sweeps <= 0) max_sweeps = 60;
     hipError_t e = hipSetDevice(c->device);
     if (e != hipSuccess) return c->hip_fail(e, "hipSetDevice");
+    const size_t esz = dtype == BSVD_F64 ? 8 : 4;
 
-    // Validate and plan: group instances by kernel configuration.
-    std::map<std::pair<int, int>, std::vector<int>> bins;
+    // ---- validate and plan -------------------------------------------------------------
+    std::vector<int> use_qr(batch, 0);
+    std::vector<JKey> jkey(batch);
+    std::vector<QKey> qkey(batch);
+    int nqr = 0;
     for (int b = 0; b < batch; ++b) {
         if (m[b] < 1) return c->fail(BSVD_EARG, "instance %d: m = %d < 1", b, m[b]);
         if (n[b] < 1) return c->fail(BSVD_EARG, "instance %d: n = %d < 1", b, n[b]);
@@ -155,54 +222,240 @@ int batched_svd(bsvd_ctx *ctx, int dtype, int batch, const int *m, const int *n,
         if (V && V[b] && ldv[b] < n[b]) return c->fail(BSVD_EARG, "instance %d: ldv = %d < n = %d", b, ldv[b], n[b]);
         const int M = m[b] >= n[b] ? m[b] : n[b];
         const int N = m[b] >= n[b] ? n[b] : m[b];
-        int mmax = 0, np = 0;
-        if (flags & (BSVD_SVD_FORCE_LDS | BSVD_SVD_FORCE_BLOCK | BSVD_SVD_QR_FIRST))
-            return c->fail(BSVD_EUNSUP, "instance %d: requested kernel path is not available", b);
-        if (!jacobi_wave_supported(dtype, M, N, &mmax, &np))
-            return c->fail(BSVD_EUNSUP, "instance %d: %d x %d has no Jacobi kernel", b, m[b], n[b]);
-        bins[{mmax, np}].push_back(b);
+        bool qr = false;
+        if (!(flags & BSVD_SVD_NO_QR) && ((flags & BSVD_SVD_QR_FIRST) || M > N)) {
+            int nb, sg, kr;
+            if (qr_config(M, N, &nb, &sg, &kr)) {
+                qr = true;
+                qkey[b] = QKey{nb, sg, kr};
+            } else if (flags & BSVD_SVD_QR_FIRST) {
+                return c->fail(BSVD_EUNSUP, "instance %d: no QR kernel for %d x %d", b, M, N);
+            }
+        }
+        use_qr[b] = qr ? 1 : 0;
+        nqr += qr ? 1 : 0;
+        int rc = choose_jacobi(dtype, qr ? N : M, N, flags, &jkey[b]);
+        if (rc) return c->fail(rc, "instance %d: %d x %d has no Jacobi kernel for the requested path", b, m[b], n[b]);
     }
 
-    const size_t desc_bytes = sizeof(SvdDesc) * (size_t)batch;
-    const size_t list_off = (desc_bytes + 255) & ~(size_t)255;
-    const size_t total = list_off + sizeof(int) * (size_t)batch;
-    int rc = c->ensure_device(total);
-    if (rc) return rc;
-    rc = c->ensure_host(total);
-    if (rc) return rc;
-
-    SvdDesc *hd = reinterpret_cast<SvdDesc *>(c->hws);
+    // ---- workspace layout: [descriptors + lists | per-instance intermediates] ------------
+    Arena up;
+    const size_t o_sd = up.alloc(sizeof(SvdDesc) * (size_t)batch);
+    const size_t o_qd = up.alloc(sizeof(QrDesc) * (size_t)(nqr ? nqr : 1));
+    const size_t o_gd = up.alloc(sizeof(GemmDesc) * (size_t)(nqr ? nqr : 1));
+    const size_t o_jl = up.alloc(sizeof(int) * (size_t)batch);
+    const size_t o_ql = up.alloc(sizeof(int) * (size_t)(nqr ? nqr : 1));
+    const size_t o_gl = up.alloc(sizeof(int) * (size_t)(nqr ? nqr : 1));
+    Arena wk;
+    wk.off = up.off;
+    std::vector<size_t> o_q(batch, 0), o_r(batch, 0), o_ur(batch, 0);
     for (int b = 0; b < batch; ++b) {
-        SvdDesc &d = hd[b];
-        d.A = A[b];
+        if (!use_qr[b]) continue;
+        const size_t M = m[b] >= n[b] ? m[b] : n[b];
+        const size_t N = m[b] >= n[b] ? n[b] : m[b];
+        o_q[b] = wk.alloc(esz * M * N);
+        o_r[b] = wk.alloc(esz * N * N);
+        o_ur[b] = wk.alloc(esz * N * N);
+    }
+    int rc = c->ensure_device(wk.off);
+    if (rc) return rc;
+    rc = c->ensure_host(up.off);
+    if (rc) return rc;
+    char *hb = static_cast<char *>(c->hws);
+    char *db = static_cast<char *>(c->dws);
+
+    SvdDesc *sd = reinterpret_cast<SvdDesc *>(hb + o_sd);
+    QrDesc *qd = reinterpret_cast<QrDesc *>(hb + o_qd);
+    GemmDesc *gd = reinterpret_cast<GemmDesc *>(hb + o_gd);
+    int qi = 0;
+    for (int b = 0; b < batch; ++b) {
+        const int trans0 = m[b] < n[b] ? 1 : 0;
+        const int M = trans0 ? n[b] : m[b];
+        const int N = trans0 ? m[b] : n[b];
+        void *Ub = (U && U[b]) ? U[b] : nullptr;
+        void *Vb = (V && V[b]) ? V[b] : nullptr;
+        const int ldub = Ub ? ldu[b] : 0, ldvb = Vb ? ldv[b] : 0;
+        // destinations of the working matrix's left / right factors
+        void *Lw = trans0 ? Vb : Ub;
+        const int ldlw = trans0 ? ldvb : ldub;
+        void *Rw = trans0 ? Ub : Vb;
+        const int ldrw = trans0 ? ldub : ldvb;
+        SvdDesc &d = sd[b];
+        if (!use_qr[b]) {
+            d.A = A[b];
+            d.S = S[b];
+            d.U = Ub;
+            d.V = Vb;
+            d.m = m[b];
+            d.n = n[b];
+            d.lda = lda[b];
+            d.ldu = ldub;
+            d.ldv = ldvb;
+            d.trans = trans0;
+            d.M = M;
+            d.N = N;
+            continue;
+        }
+        // W = Q R; one-sided Jacobi on R^T (default) or R; U_W = Q U_R, V_W = V_R
+        QrDesc &q = qd[qi];
+        q.A = A[b];
+        q.m = M;
+        q.n = N;
+        q.lda = lda[b];
+        q.trans = trans0;
+        q.Q = Lw ? db + o_q[b] : nullptr;
+        q.ldq = M;
+        q.R = db + o_r[b];
+        q.ldr = N;
+        const bool onR = (flags & BSVD_SVD_JACOBI_ON_R) != 0;
+        d.A = db + o_r[b];
         d.S = S[b];
-        d.U = U ? U[b] : nullptr;
-        d.V = V ? V[b] : nullptr;
-        d.m = m[b];
-        d.n = n[b];
-        d.lda = lda[b];
-        d.ldu = (U && U[b]) ? ldu[b] : 0;
-        d.ldv = (V && V[b]) ? ldv[b] : 0;
-        d.trans = m[b] < n[b] ? 1 : 0;
-        d.M = d.trans ? n[b] : m[b];
-        d.N = d.trans ? m[b] : n[b];
+        d.m = N;
+        d.n = N;
+        d.lda = N;
+        d.trans = onR ? 0 : 1;
+        d.M = N;
+        d.N = N;
+        // with trans = 1 the kernel sends the accumulated rotations to d.U and the normalised
+        // columns to d.V, so d.U is U_R and d.V is V_R in both cases
+        d.U = Lw ? db + o_ur[b] : nullptr;
+        d.ldu = N;
+        d.V = Rw;
+        d.ldv = ldrw;
+        GemmDesc &g = gd[qi];
+        g.A = db + o_q[b];
+        g.B = db + o_ur[b];
+        g.C = Lw;
+        g.M = M;
+        g.N = N;
+        g.K = N;
+        g.lda = M;
+        g.ldb = N;
+        g.ldc = ldlw;
+        ++qi;
     }
-    int *hl = reinterpret_cast<int *>(static_cast<char *>(c->hws) + list_off);
-    std::vector<std::pair<std::pair<int, int>, std::pair<int, int>>> launches;  // key -> (offset, count)
+    // bins
+    std::map<JKey, std::vector<int>> jb;
+    std::map<QKey, std::vector<int>> qb;
+    std::vector<int> glist;
+    qi = 0;
+    for (int b = 0; b < batch; ++b) {
+        jb[jkey[b]].push_back(b);
+        if (use_qr[b]) {
+            qb[qkey[b]].push_back(qi);
+            if (qd[qi].Q) glist.push_back(qi);
+            ++qi;
+        }
+    }
+    int *jl = reinterpret_cast<int *>(hb + o_jl);
+    int *ql = reinterpret_cast<int *>(hb + o_ql);
+    int *gl = reinterpret_cast<int *>(hb + o_gl);
+    std::vector<std::pair<JKey, std::pair<int, int>>> jlaunch;
+    std::vector<std::pair<QKey, std::pair<int, int>>> qlaunch;
     int off = 0;
-    for (auto &kv : bins) {
-        launches.push_back({kv.first, {off, (int)kv.second.size()}});
-        for (int b : kv.second) hl[off++] = b;
+    for (auto &kv : jb) {
+        jlaunch.push_back({kv.first, {off, (int)kv.second.size()}});
+        for (int b : kv.second) jl[off++] = b;
     }
-    rc = c->upload(total);
+    off = 0;
+    for (auto &kv : qb) {
+        qlaunch.push_back({kv.first, {off, (int)kv.second.size()}});
+        for (int b : kv.second) ql[off++] = b;
+    }
+    for (size_t i = 0; i < glist.size(); ++i) gl[i] = glist[i];
+    rc = c->upload(up.off);
     if (rc) return rc;
 
-    const SvdDesc *dd = reinterpret_cast<const SvdDesc *>(c->dws);
-    const int *dl = reinterpret_cast<const int *>(static_cast<char *>(c->dws) + list_off);
-    for (auto &L : launches) {
-        e = launch_jacobi_wave(dtype, L.first.first, L.first.second, dd, dl + L.second.first, L.second.second, tol,
-                               max_sweeps, sweeps, info, c->stream);
-        if (e != hipSuccess) return c->hip_fail(e, "jacobi_wave launch");
+    // ---- launch: QR, Jacobi, back-transform -----------------------------------------------
+    const QrDesc *dqd = reinterpret_cast<const QrDesc *>(db + o_qd);
+    const SvdDesc *dsd = reinterpret_cast<const SvdDesc *>(db + o_sd);
+    const GemmDesc *dgd = reinterpret_cast<const GemmDesc *>(db + o_gd);
+    const int *djl = reinterpret_cast<const int *>(db + o_jl);
+    const int *dql = reinterpret_cast<const int *>(db + o_ql);
+    const int *dgl = reinterpret_cast<const int *>(db + o_gl);
+    for (auto &L : qlaunch) {
+        e = launch_qr(dtype, L.first.nb, L.first.seg, L.first.kr, dqd, dql + L.second.first, L.second.second,
+                      c->stream);
+        if (e != hipSuccess) return c->hip_fail(e, "qr launch");
+    }
+    for (auto &L : jlaunch) {
+        if (L.first.kind == JK_WAVE)
+            e = launch_jacobi_wave(dtype, L.first.a, L.first.b, dsd, djl + L.second.first, L.second.second, tol,
+                                   max_sweeps, sweeps, info, c->stream);
+        else
+            e = launch_jacobi_lds(dtype, L.first.a, L.first.b, dsd, djl + L.second.first, L.second.second, tol,
+                                  max_sweeps, sweeps, info, c->stream);
+        if (e != hipSuccess) return c->hip_fail(e, "jacobi launch");
+    }
+    if (!glist.empty()) {
+        e = launch_gemm_small(dtype, dgd, dgl, (int)glist.size(), c->stream);
+        if (e != hipSuccess) return c->hip_fail(e, "gemm launch");
+    }
+    return BSVD_OK;
+}
+
+int batched_qr(bsvd_ctx *ctx, int dtype, int batch, const int *m, const int *n, const void *const *A,
+               const int *lda, void *const *Q, const int *ldq, void *const *R, const int *ldr) {
+    if (!ctx) return BSVD_EARG;
+    Ctx *c = reinterpret_cast<Ctx *>(ctx);
+    c->err.clear();
+    if (dtype != BSVD_F64 && dtype != BSVD_F32) return c->fail(BSVD_EARG, "dtype %d is not BSVD_F64/BSVD_F32", dtype);
+    if (batch < 0) return c->fail(BSVD_EARG, "batch = %d < 0", batch);
+    if (batch == 0) return BSVD_OK;
+    if (!m || !n || !A || !lda) return c->fail(BSVD_EARG, "m, n, A and lda must be non-NULL");
+    if (Q && !ldq) return c->fail(BSVD_EARG, "Q given without ldq");
+    if (R && !ldr) return c->fail(BSVD_EARG, "R given without ldr");
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return c->hip_fail(e, "hipSetDevice");
+    std::map<QKey, std::vector<int>> qb;
+    for (int b = 0; b < batch; ++b) {
+        if (m[b] < 1) return c->fail(BSVD_EARG, "instance %d: m = %d < 1", b, m[b]);
+        if (n[b] < 1) return c->fail(BSVD_EARG, "instance %d: n = %d < 1", b, n[b]);
+        if (lda[b] < m[b]) return c->fail(BSVD_EARG, "instance %d: lda = %d < m = %d", b, lda[b], m[b]);
+        if (!A[b]) return c->fail(BSVD_EARG, "instance %d: A is NULL", b);
+        const int k = m[b] < n[b] ? m[b] : n[b];
+        if (Q && Q[b] && ldq[b] < m[b]) return c->fail(BSVD_EARG, "instance %d: ldq = %d < m = %d", b, ldq[b], m[b]);
+        if (R && R[b] && ldr[b] < k) return c->fail(BSVD_EARG, "instance %d: ldr = %d < min(m, n) = %d", b, ldr[b], k);
+        QKey key;
+        if (!qr_config(m[b], n[b], &key.nb, &key.seg, &key.kr))
+            return c->fail(BSVD_EUNSUP, "instance %d: no QR kernel for %d x %d (needs m <= 512, n <= 64)", b, m[b], n[b]);
+        qb[key].push_back(b);
+    }
+    Arena up;
+    const size_t o_qd = up.alloc(sizeof(QrDesc) * (size_t)batch);
+    const size_t o_ql = up.alloc(sizeof(int) * (size_t)batch);
+    int rc = c->ensure_device(up.off);
+    if (rc) return rc;
+    rc = c->ensure_host(up.off);
+    if (rc) return rc;
+    char *hb = static_cast<char *>(c->hws);
+    char *db = static_cast<char *>(c->dws);
+    QrDesc *qd = reinterpret_cast<QrDesc *>(hb + o_qd);
+    for (int b = 0; b < batch; ++b) {
+        QrDesc &q = qd[b];
+        q.A = A[b];
+        q.m = m[b];
+        q.n = n[b];
+        q.lda = lda[b];
+        q.trans = 0;
+        q.Q = (Q && Q[b]) ? Q[b] : nullptr;
+        q.ldq = q.Q ? ldq[b] : 0;
+        q.R = (R && R[b]) ? R[b] : nullptr;
+        q.ldr = q.R ? ldr[b] : 0;
+    }
+    int *ql = reinterpret_cast<int *>(hb + o_ql);
+    std::vector<std::pair<QKey, std::pair<int, int>>> qlaunch;
+    int off = 0;
+    for (auto &kv : qb) {
+        qlaunch.push_back({kv.first, {off, (int)kv.second.size()}});
+        for (int b : kv.second) ql[off++] = b;
+    }
+    rc = c->upload(up.off);
+    if (rc) return rc;
+    for (auto &L : qlaunch) {
+        e = launch_qr(dtype, L.first.nb, L.first.seg, L.first.kr, reinterpret_cast<const QrDesc *>(db + o_qd),
+                      reinterpret_cast<const int *>(db + o_ql) + L.second.first, L.second.second, c->stream);
+        if (e != hipSuccess) return c->hip_fail(e, "qr launch");
     }
     return BSVD_OK;
 }

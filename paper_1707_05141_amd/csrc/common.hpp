@@ -18,6 +18,25 @@ struct SvdDesc {
     int M, N;
 };
 
+// Per-instance descriptor of a batched Householder QR: A (m x n) -> thin Q (m x k), R (k x n),
+// k = min(m, n); Q or R may be NULL.
+// trans = 1 factors A^T (A is then n x m in memory with leading dimension lda).
+struct QrDesc {
+    const void *A;
+    void *Q;
+    void *R;
+    int m, n, lda, ldq, ldr;
+    int trans;
+};
+
+// Per-instance descriptor of a small GEMM C (M x N) = A (M x K) B (K x N), column-major.
+struct GemmDesc {
+    const void *A;
+    const void *B;
+    void *C;
+    int M, N, K, lda, ldb, ldc;
+};
+
 // Per-instance info codes (see bsvd.h).
 enum { INFO_OK = 0, INFO_SWEEPS = 1, INFO_RANKCAP = 2, INFO_NONFINITE = 3 };
 
@@ -25,5 +44,12 @@ enum { INFO_OK = 0, INFO_SWEEPS = 1, INFO_RANKCAP = 2, INFO_NONFINITE = 3 };
 hipError_t launch_jacobi_wave(int dtype, int mmax, int np, const SvdDesc *d, const int *list, int count,
                               double tol, int max_sweeps, int *sweeps, int *info, hipStream_t st);
 bool jacobi_wave_supported(int dtype, int M, int N, int *mmax, int *np);
+bool qr_config(int m, int n, int *nb, int *seg, int *kr);
+hipError_t launch_qr(int dtype, int nb, int seg, int kr, const QrDesc *d, const int *list, int count,
+                     hipStream_t st);
+bool jacobi_lds_supported(int dtype, int M, int N, int *mmax, int *nmax);
+hipError_t launch_jacobi_lds(int dtype, int mmax, int nmax, const SvdDesc *d, const int *list, int count, double tol,
+                             int max_sweeps, int *sweeps, int *info, hipStream_t st);
+hipError_t launch_gemm_small(int dtype, const GemmDesc *d, const int *list, int count, hipStream_t st);
 
 }  // namespace bsvd

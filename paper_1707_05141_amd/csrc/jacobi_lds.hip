@@ -1,0 +1,235 @@
+// LDS-resident one-sided Jacobi SVD (shared-memory kernel of Section 5), gfx950.
+//
+// One 256-thread workgroup per matrix. The working matrix (M x N) and V (N x N) live in LDS
+// (160 KB per CU on gfx950: 64 x 64 FP64 with its V takes 64 KB, 128 x 128 FP32 takes 128 KB).
+// Each round-robin step processes the N/2 disjoint column pairs of the step at once (Section 5
+// assigns one warp per pair); here each pair gets LPP = 512 / N consecutive lanes, and each lane
+// handles the rows r = l, l + LPP, ... of both columns: the three Gram entries are lane-local
+// partial sums reduced over the LPP lanes with shuffles (Section 5's serial pre-reduction followed
+// by warp shuffles), the rotation is derived redundantly by the LPP lanes, and the lanes rotate
+// their rows of the two columns of A and of V. One barrier separates consecutive steps.
+//
+// Precision: T = double, or T = float with dot products, norms, angle and test in double.
+
+#include "common.hpp"
+#include "jacobi_device.hpp"
+
+namespace bsvd {
+
+template <int LPP>
+__device__ __forceinline__ double grp_sum(double v) {
+#pragma unroll
+    for (int o = LPP / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+template <typename T, int MMAX, int NMAX>
+__global__ __launch_bounds__(256) void jacobi_lds_kernel(const SvdDesc *__restrict__ descs, const int *__restrict__ list,
+                                                         double tol, int max_sweeps, int *__restrict__ sweeps_out,
+                                                         int *__restrict__ info_out) {
+    constexpr int NT = 256;
+    constexpr int NPAIR = NMAX / 2;
+    constexpr int LPP = NT / NPAIR;  // lanes per pair
+    constexpr int RPL = (MMAX + LPP - 1) / LPP;  // rows of A per lane
+    constexpr int VPL = (NMAX + LPP - 1) / LPP;  // rows of V per lane
+    constexpr int LDA = MMAX + 1;
+    constexpr int LDV = NMAX + 1;
+    static_assert(LPP >= 1 && LPP <= 64, "lanes per pair");
+
+    extern __shared__ unsigned char smem_raw[];
+    T *sA = reinterpret_cast<T *>(smem_raw);
+    T *sV = sA + (size_t)LDA * NMAX;
+    __shared__ double snorm[NMAX];
+    __shared__ int sflag;
+
+    const int inst = list[blockIdx.x];
+    const SvdDesc D = descs[inst];
+    const int t = threadIdx.x;
+    const int M = D.M, N = D.N;
+    // columns padded to an even count: the circle schedule runs on NP = N rounded up to even
+    const int NP = (N + 1) & ~1;
+
+    // load working matrix (zero padding) and V = I
+    const T *Ap = static_cast<const T *>(D.A);
+    int nonfinite = 0;
+    for (int idx = t; idx < LDA * NMAX; idx += NT) {
+        const int c = idx / LDA, r = idx - c * LDA;
+        T x = T(0);
+        if (c < N && r < M) x = D.trans ? Ap[c + (size_t)r * D.lda] : Ap[r + (size_t)c * D.lda];
+        if (!__builtin_isfinite(x)) nonfinite = 1;
+        sA[idx] = x;
+    }
+    for (int idx = t; idx < LDV * NMAX; idx += NT) {
+        const int c = idx / LDV, r = idx - c * LDV;
+        sV[idx] = (r == c && c < N) ? T(1) : T(0);
+    }
+    const int bad = __syncthreads_or(nonfinite);
+
+    const int g = t / LPP;  // pair slot
+    const int l = t - g * LPP;
+    int sweeps = 0;
+    bool converged = false;
+    if (!bad) {
+        for (int sw = 0; sw < max_sweeps; ++sw) {
+            int rotated = 0;
+            for (int s = 0; s < NP - 1; ++s) {
+                int p, q;
+                if (g == 0) {
+                    p = s;
+                    q = NP - 1;
+                } else {
+                    const int L = NP - 1;
+                    p = (s + g) % L;
+                    q = ((s - g) % L + L) % L;
+                }
+                const int i = p < q ? p : q;
+                const int j = p < q ? q : p;
+                const bool live = g < NP / 2;
+                double alpha = 0.0, beta = 0.0, gam = 0.0;
+                T ai[RPL], aj[RPL];
+                if (live) {
+#pragma unroll
+                    for (int k = 0; k < RPL; ++k) {
+                        const int r = l + LPP * k;
+                        ai[k] = (r < MMAX) ? sA[r + i * LDA] : T(0);
+                        aj[k] = (r < MMAX) ? sA[r + j * LDA] : T(0);
+                        alpha = fma((double)ai[k], (double)ai[k], alpha);
+                        beta = fma((double)aj[k], (double)aj[k], beta);
+                        gam = fma((double)ai[k], (double)aj[k], gam);
+                    }
+                }
+                alpha = grp_sum<LPP>(alpha);
+                beta = grp_sum<LPP>(beta);
+                gam = grp_sum<LPP>(gam);
+                const bool rot = live && alpha > 0.0 && beta > 0.0 && fabs(gam) > tol * sqrt(alpha * beta);
+                if (rot) {
+                    double c, sn;
+                    jacobi_rot(alpha, beta, gam, c, sn);
+                    const T cc = (T)c, ss = (T)sn;
+#pragma unroll
+                    for (int k = 0; k < RPL; ++k) {
+                        const int r = l + LPP * k;
+                        if (r < MMAX) {
+                            sA[r + i * LDA] = cc * ai[k] - ss * aj[k];
+                            sA[r + j * LDA] = ss * ai[k] + cc * aj[k];
+                        }
+                    }
+#pragma unroll
+                    for (int k = 0; k < VPL; ++k) {
+                        const int r = l + LPP * k;
+                        if (r < NMAX) {
+                            const T vi = sV[r + i * LDV], vj = sV[r + j * LDV];
+                            sV[r + i * LDV] = cc * vi - ss * vj;
+                            sV[r + j * LDV] = ss * vi + cc * vj;
+                        }
+                    }
+                    rotated = 1;
+                }
+                __syncthreads();
+            }
+            sweeps = sw + 1;
+            if (!__syncthreads_or(rotated)) {
+                converged = true;
+                break;
+            }
+        }
+    }
+
+    // column norms
+    for (int c = t / 4; c < NMAX; c += NT / 4) {
+        const int part = t & 3;
+        double s = 0.0;
+        for (int r = part; r < MMAX; r += 4) s = fma((double)sA[r + c * LDA], (double)sA[r + c * LDA], s);
+        s += __shfl_xor(s, 1, 64);
+        s += __shfl_xor(s, 2, 64);
+        if (part == 0) snorm[c] = sqrt(s);
+    }
+    __syncthreads();
+
+    T *S = static_cast<T *>(D.S);
+    if (bad) {
+        for (int c = t; c < N; c += NT) S[c] = (T)__builtin_nan("");
+    } else {
+        T *Lf = static_cast<T *>(D.trans ? D.V : D.U);
+        const int ldl = D.trans ? D.ldv : D.ldu;
+        T *Rf = static_cast<T *>(D.trans ? D.U : D.V);
+        const int ldr = D.trans ? D.ldu : D.ldv;
+        // each group of 4 threads handles one column: rank by descending norm (stable)
+        for (int c = t / 4; c < N; c += NT / 4) {
+            const int part = t & 3;
+            const double sc = snorm[c];
+            int rank = 0;
+            for (int q = 0; q < N; ++q) {
+                const double sq = snorm[q];
+                rank += (sq > sc || (sq == sc && q < c)) ? 1 : 0;
+            }
+            if (part == 0) S[rank] = (T)sc;
+            if (Lf) {
+                const double inv = sc > 0.0 ? 1.0 / sc : 0.0;
+                for (int r = part; r < M; r += 4) Lf[r + (size_t)rank * ldl] = (T)((double)sA[r + c * LDA] * inv);
+            }
+            if (Rf)
+                for (int r = part; r < N; r += 4) Rf[r + (size_t)rank * ldr] = sV[r + c * LDV];
+        }
+    }
+    if (t == 0) {
+        if (info_out) info_out[inst] = bad ? INFO_NONFINITE : (converged ? INFO_OK : INFO_SWEEPS);
+        if (sweeps_out) sweeps_out[inst] = bad ? 0 : sweeps;
+    }
+}
+
+bool jacobi_lds_supported(int dtype, int M, int N, int *mmax, int *nmax) {
+    int NMAXv = 8;
+    while (NMAXv < N) NMAXv <<= 1;
+    int MMAXv = NMAXv;
+    while (MMAXv < M) MMAXv <<= 1;
+    const size_t esz = dtype == 0 ? 8 : 4;
+    const size_t bytes = esz * ((size_t)(MMAXv + 1) * NMAXv + (size_t)(NMAXv + 1) * NMAXv);
+    if (NMAXv > (dtype == 0 ? 64 : 128) || MMAXv > 128 || bytes > 150 * 1024) return false;
+    *mmax = MMAXv;
+    *nmax = NMAXv;
+    return true;
+}
+
+template <typename T, int MMAX, int NMAX>
+static hipError_t lds_launch_one(const SvdDesc *d, const int *list, int count, double tol, int max_sweeps, int *sw,
+                                 int *info, hipStream_t st) {
+    const size_t bytes = sizeof(T) * ((size_t)(MMAX + 1) * NMAX + (size_t)(NMAX + 1) * NMAX);
+    auto kern = jacobi_lds_kernel<T, MMAX, NMAX>;
+    hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3(count), dim3(256), bytes, st, d, list, tol, max_sweeps, sw, info);
+    return hipGetLastError();
+}
+
+#define BSVD_LDS_CASE(MM, NN)                                                                        \
+    if (mmax == MM && nmax == NN) {                                                                  \
+        if (dtype == 0) {                                                                            \
+            if constexpr (NN <= 64) return lds_launch_one<double, MM, NN>(d, list, count, tol, max_sweeps, sweeps, info, st); \
+            return hipErrorInvalidValue;                                                              \
+        }                                                                                            \
+        return lds_launch_one<float, MM, NN>(d, list, count, tol, max_sweeps, sweeps, info, st);     \
+    }
+
+hipError_t launch_jacobi_lds(int dtype, int mmax, int nmax, const SvdDesc *d, const int *list, int count, double tol,
+                             int max_sweeps, int *sweeps, int *info, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    BSVD_LDS_CASE(8, 8)
+    BSVD_LDS_CASE(16, 8)
+    BSVD_LDS_CASE(32, 8)
+    BSVD_LDS_CASE(64, 8)
+    BSVD_LDS_CASE(128, 8)
+    BSVD_LDS_CASE(16, 16)
+    BSVD_LDS_CASE(32, 16)
+    BSVD_LDS_CASE(64, 16)
+    BSVD_LDS_CASE(128, 16)
+    BSVD_LDS_CASE(32, 32)
+    BSVD_LDS_CASE(64, 32)
+    BSVD_LDS_CASE(128, 32)
+    BSVD_LDS_CASE(64, 64)
+    BSVD_LDS_CASE(128, 64)
+    BSVD_LDS_CASE(128, 128)
+    return hipErrorInvalidValue;
+}
+
+}  // namespace bsvd

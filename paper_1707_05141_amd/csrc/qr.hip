@@ -1,0 +1,227 @@
+// Batched Householder QR (Section 2.1 Algorithm 1; Section 3.1 kernel design), gfx950.
+//
+// One workgroup factors one matrix (m <= SEG * KR rows, n <= NB columns). Thread (c, seg) owns
+// column c and the rows seg, seg + SEG, seg + 2 SEG, ... of it in registers, so a column is spread
+// over SEG consecutive lanes and every column operation (norm, v^T x, rank-1 update) is a
+// lane-local serial sum followed by a log2(SEG)-step shuffle reduction; no reduction over the
+// whole workgroup is needed. For each column j the owning lanes publish the column in LDS, every
+// thread derives the reflector from its norm, and the lanes of the trailing columns apply
+// I - 2 v v^T to their own registers. The reflectors overwrite the factored columns in place
+// (compact [R; V] storage), R is written out, and the thin Q = H_0 H_1 ... H_{k-1} [I; 0] is then
+// formed in place by applying the reflectors in reverse order.
+//
+// Reading of house(): beta = -sign(alpha) ||x|| (sign(0) = +1); a column whose sub-diagonal part
+// is exactly zero, or of length one, gets H = I.
+
+#include "common.hpp"
+
+namespace bsvd {
+
+template <typename T, int SEG>
+__device__ __forceinline__ T seg_sum(T v) {
+#pragma unroll
+    for (int o = SEG / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+template <typename T, int NB, int SEG, int KR>
+__global__ __launch_bounds__(NB *SEG) void qr_kernel(const QrDesc *__restrict__ descs, const int *__restrict__ list) {
+    __shared__ T vbuf[SEG * KR];
+    __shared__ T diag[NB];
+    __shared__ int skipf[NB];
+    __shared__ T s2sh;
+
+    const int inst = list[blockIdx.x];
+    const QrDesc D = descs[inst];
+    const int t = threadIdx.x;
+    const int c = t / SEG;
+    const int seg = t - c * SEG;
+    const int m = D.m, n = D.n;
+    const int k = m < n ? m : n;
+    const bool colok = c < n;
+
+    T x[KR];
+    const T *A = static_cast<const T *>(D.A);
+#pragma unroll
+    for (int kk = 0; kk < KR; ++kk) {
+        const int row = seg + SEG * kk;
+        x[kk] = (colok && row < m) ? (D.trans ? A[c + (size_t)row * D.lda] : A[row + (size_t)c * D.lda]) : T(0);
+    }
+
+    // ---- factorisation -------------------------------------------------------------------
+    for (int j = 0; j < k; ++j) {
+        if (c == j) {
+            T part = T(0);
+#pragma unroll
+            for (int kk = 0; kk < KR; ++kk) {
+                const int row = seg + SEG * kk;
+                if (row < m) {
+                    vbuf[row] = x[kk];
+                    if (row > j) part += x[kk] * x[kk];
+                }
+            }
+            part = seg_sum<T, SEG>(part);
+            if (seg == 0) s2sh = part;
+        }
+        __syncthreads();
+        const T s2 = s2sh;
+        const T alpha = vbuf[j];
+        const bool skip = (m - j < 2) || (s2 == T(0));
+        T beta = alpha, vj = T(0), inv = T(0);
+        if (!skip) {
+            const T nu = sqrt(alpha * alpha + s2);
+            beta = alpha >= T(0) ? -nu : nu;
+            vj = alpha - beta;
+            inv = T(1) / sqrt(vj * vj + s2);
+        }
+        if (!skip && colok && c > j) {
+            T w = T(0);
+#pragma unroll
+            for (int kk = 0; kk < KR; ++kk) {
+                const int row = seg + SEG * kk;
+                if (row >= j && row < m) w += ((row == j) ? vj : vbuf[row]) * x[kk];
+            }
+            w = seg_sum<T, SEG>(w) * inv;
+            const T w2 = T(2) * w * inv;
+#pragma unroll
+            for (int kk = 0; kk < KR; ++kk) {
+                const int row = seg + SEG * kk;
+                if (row >= j && row < m) x[kk] -= w2 * ((row == j) ? vj : vbuf[row]);
+            }
+        }
+        if (c == j) {
+#pragma unroll
+            for (int kk = 0; kk < KR; ++kk) {
+                const int row = seg + SEG * kk;
+                if (row >= j && row < m) x[kk] = skip ? T(0) : ((row == j) ? vj : x[kk]) * inv;
+            }
+            if (seg == 0) {
+                diag[j] = beta;
+                skipf[j] = skip ? 1 : 0;
+            }
+        }
+        __syncthreads();
+    }
+
+    // ---- R (k x n, upper trapezoidal) ------------------------------------------------------
+    if (D.R && colok) {
+        T *R = static_cast<T *>(D.R);
+#pragma unroll
+        for (int kk = 0; kk < KR; ++kk) {
+            const int row = seg + SEG * kk;
+            if (row < k) R[row + (size_t)c * D.ldr] = row < c ? x[kk] : (row == c ? diag[c] : T(0));
+        }
+    }
+    if (!D.Q) return;
+
+    // ---- thin Q by backward accumulation, in place ---------------------------------------
+    for (int j = k - 1; j >= 0; --j) {
+        if (c == j) {
+#pragma unroll
+            for (int kk = 0; kk < KR; ++kk) {
+                const int row = seg + SEG * kk;
+                if (row >= j && row < m) vbuf[row] = x[kk];
+            }
+        }
+        __syncthreads();
+        const bool skip = skipf[j] != 0;
+        if (!skip && c > j && c < k) {
+            T w = T(0);
+#pragma unroll
+            for (int kk = 0; kk < KR; ++kk) {
+                const int row = seg + SEG * kk;
+                if (row >= j && row < m) w += vbuf[row] * x[kk];
+            }
+            w = T(2) * seg_sum<T, SEG>(w);
+#pragma unroll
+            for (int kk = 0; kk < KR; ++kk) {
+                const int row = seg + SEG * kk;
+                if (row >= j && row < m) x[kk] -= w * vbuf[row];
+            }
+        }
+        if (c == j) {
+            const T vjj = vbuf[j];
+#pragma unroll
+            for (int kk = 0; kk < KR; ++kk) {
+                const int row = seg + SEG * kk;
+                if (row < m) {
+                    const T e = (row == j) ? T(1) : T(0);
+                    x[kk] = row < j ? T(0) : (skip ? e : e - T(2) * vbuf[row] * vjj);
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (c < k) {
+        T *Q = static_cast<T *>(D.Q);
+#pragma unroll
+        for (int kk = 0; kk < KR; ++kk) {
+            const int row = seg + SEG * kk;
+            if (row < m) Q[row + (size_t)c * D.ldq] = x[kk];
+        }
+    }
+}
+
+// Shape selection: NB = next power of two >= n (at least 8), SEG the smallest power of two with
+// SEG * 64 >= m and NB * SEG >= 64, KR = next power of two >= ceil(m / SEG) (at least 8).
+static int p2(int x) {
+    int p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+bool qr_config(int m, int n, int *nb, int *seg, int *kr) {
+    int NB = p2(n < 8 ? 8 : n);
+    if (NB > 64 || m > 512 || m < 1 || n < 1) return false;
+    int SEG = 1;
+    while (SEG * 64 < m || NB * SEG < 64) SEG <<= 1;
+    if (NB * SEG > 512) return false;
+    int KR = p2((m + SEG - 1) / SEG);
+    if (KR < 8) KR = 8;
+    if (KR > 64) return false;
+    *nb = NB;
+    *seg = SEG;
+    *kr = KR;
+    return true;
+}
+
+template <typename T, int NB, int SEG, int KR>
+static hipError_t qr_launch_one(const QrDesc *d, const int *list, int count, hipStream_t st) {
+    hipLaunchKernelGGL((qr_kernel<T, NB, SEG, KR>), dim3(count), dim3(NB * SEG), 0, st, d, list);
+    return hipGetLastError();
+}
+
+#define BSVD_QR_CASE(NB, SEG, KR)                                                     \
+    if (nb == NB && seg == SEG && kr == KR)                                          \
+        return dtype == 0 ? qr_launch_one<double, NB, SEG, KR>(d, list, count, st)  \
+                          : qr_launch_one<float, NB, SEG, KR>(d, list, count, st);
+
+hipError_t launch_qr(int dtype, int nb, int seg, int kr, const QrDesc *d, const int *list, int count,
+                     hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    BSVD_QR_CASE(8, 8, 8)
+    BSVD_QR_CASE(8, 8, 16)
+    BSVD_QR_CASE(8, 8, 32)
+    BSVD_QR_CASE(8, 8, 64)
+    BSVD_QR_CASE(16, 4, 8)
+    BSVD_QR_CASE(16, 4, 16)
+    BSVD_QR_CASE(16, 4, 32)
+    BSVD_QR_CASE(16, 4, 64)
+    BSVD_QR_CASE(16, 8, 64)
+    BSVD_QR_CASE(32, 2, 8)
+    BSVD_QR_CASE(32, 2, 16)
+    BSVD_QR_CASE(32, 2, 32)
+    BSVD_QR_CASE(32, 2, 64)
+    BSVD_QR_CASE(32, 4, 64)
+    BSVD_QR_CASE(32, 8, 64)
+    BSVD_QR_CASE(64, 1, 8)
+    BSVD_QR_CASE(64, 1, 16)
+    BSVD_QR_CASE(64, 1, 32)
+    BSVD_QR_CASE(64, 1, 64)
+    BSVD_QR_CASE(64, 2, 64)
+    BSVD_QR_CASE(64, 4, 64)
+    BSVD_QR_CASE(64, 8, 64)
+    return hipErrorInvalidValue;
+}
+
+}  // namespace bsvd

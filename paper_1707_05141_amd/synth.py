@@ -97,3 +97,26 @@ def batch_gaussian(batch: int, m: int, n: int, seed: int = 1) -> np.ndarray:
 def batch_graded(batch: int, m: int, n: int, decades: float, seed: int = 2) -> np.ndarray:
     s = graded_sigma_log(min(m, n), decades)
     return np.stack([prescribed(m, n, s, seed, i) for i in range(batch)])
+
+
+def batch_haar(rng: np.random.Generator, b: int, m: int, n: int) -> np.ndarray:
+    """b Haar-distributed m x n matrices with orthonormal columns (batched numpy QR)."""
+    G = rng.standard_normal((b, m, n))
+    Q, R = np.linalg.qr(G)
+    d = np.sign(np.einsum("bii->bi", R))
+    d[d == 0] = 1.0
+    return Q * d[:, None, :]
+
+
+def batch_prescribed(batch: int, m: int, n: int, sigma: np.ndarray, seed: int, chunk: int = 2000) -> np.ndarray:
+    """batch x (U diag(sigma) V^T) with Haar U (m x k), V (n x k); drawn in chunks from one stream
+    per (seed, m, n)."""
+    k = min(m, n)
+    rng = _rng(seed, m * 100003 + n, 11)
+    out = np.empty((batch, m, n))
+    for s0 in range(0, batch, chunk):
+        c = min(chunk, batch - s0)
+        U = batch_haar(rng, c, m, k)
+        V = batch_haar(rng, c, n, k)
+        out[s0:s0 + c] = np.matmul(U * sigma[None, None, :], np.transpose(V, (0, 2, 1)))
+    return out

@@ -1,0 +1,132 @@
+"""GPU parity of batched_qr and of the QR-first / LDS Jacobi paths of batched_svd, through the C ABI."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1707_05141_amd import synth
+from svd_checks import check_svd
+
+pytestmark = pytest.mark.gpu
+
+import paper_1707_05141_amd as P  # noqa: E402
+from paper_1707_05141_amd import _lib  # noqa: E402
+
+U64 = np.finfo(np.float64).eps
+
+
+def _qr(A_np, dtype=torch.float64):
+    A = torch.from_numpy(A_np).to(device="cuda", dtype=dtype)
+    Q, R = P.qr(A)
+    torch.cuda.synchronize()
+    return Q.double().cpu().numpy(), R.double().cpu().numpy()
+
+
+@pytest.mark.parametrize("m,n,b", [(1, 1, 2), (2, 2, 3), (5, 3, 4), (3, 5, 4), (64, 64, 7), (128, 32, 9),
+                                   (33, 17, 5), (17, 33, 5), (512, 24, 3), (511, 64, 2), (300, 8, 3), (200, 40, 3),
+                                   (64, 1, 3), (9, 64, 2), (257, 16, 2)])
+def test_qr_parity(m, n, b):
+    print("case: qr %dx%d batch %d" % (m, n, b), flush=True)
+    A = synth.batch_gaussian(b, m, n, seed=m + 1000 * n)
+    Q, R = _qr(A)
+    Qo, Ro = oracle.batched_qr(A)
+    k = min(m, n)
+    for i in range(b):
+        assert np.all(np.tril(R[i], -1) == 0.0)
+        assert np.linalg.norm(Q[i].T @ Q[i] - np.eye(k)) <= 20 * max(m, 8) * U64
+        assert np.linalg.norm(Q[i] @ R[i] - A[i]) <= 20 * max(m, 8) * U64 * np.linalg.norm(A[i])
+        # same reflector convention as the oracle: the factors agree element by element
+        np.testing.assert_allclose(R[i], Ro[i], rtol=0, atol=1e-12 * np.abs(Ro[i]).max())
+        np.testing.assert_allclose(Q[i], Qo[i], rtol=0, atol=1e-11)
+
+
+def test_qr_special_inputs():
+    A = np.zeros((3, 16, 8))
+    A[0] = np.triu(np.arange(1.0, 129.0).reshape(16, 8))  # already triangular: Q = I
+    A[1][:, 3] = 1.0  # rank one with zero columns
+    A[2] = synth.gaussian(16, 8, 1, 0)
+    Q, R = _qr(A)
+    np.testing.assert_array_equal(Q[0], np.eye(16)[:, :8])
+    np.testing.assert_array_equal(R[0], A[0][:8])
+    for i in (1, 2):
+        assert np.linalg.norm(Q[i] @ R[i] - A[i]) <= 1e-13 * max(1, np.linalg.norm(A[i]))
+        assert np.linalg.norm(Q[i].T @ Q[i] - np.eye(8)) <= 1e-13
+
+
+def test_qr_fp32():
+    A = synth.batch_gaussian(8, 128, 32, seed=3)
+    Q, R = _qr(A, torch.float32)
+    A32 = A.astype(np.float32).astype(np.float64)
+    for i in range(8):
+        assert np.linalg.norm(Q[i] @ R[i] - A32[i]) <= 1e-5 * np.linalg.norm(A32[i])
+        assert np.linalg.norm(Q[i].T @ Q[i] - np.eye(32)) <= 1e-5
+
+
+def _svd(A_np, flags=0, dtype=torch.float64):
+    A = torch.from_numpy(A_np).to(device="cuda", dtype=dtype)
+    S, U, V, sw, info = P.svd(A, flags=flags)
+    torch.cuda.synchronize()
+    return S.double().cpu().numpy(), U.double().cpu().numpy(), V.double().cpu().numpy(), sw.cpu().numpy(), info.cpu().numpy()
+
+
+@pytest.mark.parametrize("m,n,b,flags", [
+    (64, 64, 12, _lib.SVD_FORCE_LDS), (64, 48, 5, _lib.SVD_FORCE_LDS), (40, 40, 5, _lib.SVD_FORCE_LDS),
+    (128, 64, 3, _lib.SVD_FORCE_LDS | _lib.SVD_NO_QR), (64, 64, 6, _lib.SVD_QR_FIRST),
+    (128, 32, 10, 0), (32, 128, 4, 0), (64, 64, 5, _lib.SVD_QR_FIRST | _lib.SVD_JACOBI_ON_R),
+    (512, 64, 2, 0), (300, 20, 3, 0), (64, 60, 3, _lib.SVD_QR_FIRST | _lib.SVD_FORCE_LDS),
+    (32, 32, 17, _lib.SVD_QR_FIRST), (16, 16, 9, _lib.SVD_FORCE_LDS)])
+def test_svd_paths_parity(m, n, b, flags):
+    print("case: svd %dx%d batch %d flags %d" % (m, n, b, flags), flush=True)
+    k = min(m, n)
+    sig = synth.graded_sigma_log(k, 8.0)
+    A = np.stack([synth.prescribed(m, n, sig, seed=11, inst=i) for i in range(b)])
+    S, U, V, sw, info = _svd(A, flags)
+    So, Uo, Vo, swo, io = oracle.batched_jacobi_svd(A)
+    for i in range(b):
+        assert info[i] == 0
+        assert np.max(np.abs(S[i] - sig)) <= 1e-12
+        check_svd(A[i], S[i], U[i], V[i], So[i], Uo[i], Vo[i], 1e-12, vec_tol=1e-7)
+
+
+def test_lds_fp32_128():
+    """FP32 data and rotations with FP64 angles / norms, 128 x 128 in LDS."""
+    A = synth.batch_gaussian(4, 128, 128, seed=8)
+    A32 = A.astype(np.float32).astype(np.float64)
+    S, U, V, sw, info = _svd(A, _lib.SVD_FORCE_LDS, torch.float32)
+    So = oracle.batched_jacobi_svd(A32, want_vectors=False)[0]
+    assert np.all(info == 0)
+    for i in range(4):
+        assert np.max(np.abs(S[i] - So[i])) <= 1e-5 * So[i][0]
+
+
+def test_mixed_shape_batch_one_call():
+    """An uneven batch (several kernels / bins) in one call."""
+    rng = np.random.default_rng(5)
+    shapes = [(32, 32), (64, 64), (128, 32), (7, 5), (5, 7), (64, 16), (100, 50), (1, 1)] * 3
+    mats = [synth.gaussian(m, n, 4, i) for i, (m, n) in enumerate(shapes)]
+    b = len(mats)
+    dev = []
+    ptrA, ptrS, ptrU, ptrV = [], [], [], []
+    outs = []
+    for A in mats:
+        m, n = A.shape
+        k = min(m, n)
+        Ac = torch.from_numpy(np.asfortranarray(A).ravel(order="F").copy()).cuda()
+        S = torch.empty(k, dtype=torch.float64, device="cuda")
+        U = torch.empty(m * k, dtype=torch.float64, device="cuda")
+        V = torch.empty(n * k, dtype=torch.float64, device="cuda")
+        dev.append(Ac)
+        outs.append((S, U, V))
+        ptrA.append(Ac.data_ptr()); ptrS.append(S.data_ptr()); ptrU.append(U.data_ptr()); ptrV.append(V.data_ptr())
+    ms = [A.shape[0] for A in mats]
+    ns = [A.shape[1] for A in mats]
+    info = torch.empty(b, dtype=torch.int32, device="cuda")
+    P.batched_svd(ms, ns, ptrA, ms, ptrS, ptrU, ms, ptrV, ns, info=info)
+    torch.cuda.synchronize()
+    assert np.all(info.cpu().numpy() == 0)
+    for A, (S, U, V) in zip(mats, outs):
+        m, n = A.shape
+        k = min(m, n)
+        So, Uo, Vo, _, _ = oracle.jacobi_svd(A)
+        check_svd(A, S.cpu().numpy(), U.cpu().numpy().reshape(k, m).T, V.cpu().numpy().reshape(k, n).T, So, Uo, Vo,
+                  1e-12, vec_tol=1e-8)
