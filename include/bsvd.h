@@ -52,6 +52,11 @@ enum {
     BSVD_SVD_JACOBI_ON_R = 1u << 5  /* after QR, rotate the columns of R instead of its rows */
 };
 
+/* Flags for batched_rsvd. */
+enum {
+    BSVD_RSVD_FIXED = 1u << 0 /* exactly ell0[b] samples, no adaptive growth (Algorithm 4 as printed) */
+};
+
 /* Create a context bound to `device` (HIP ordinal) and `stream` (a hipStream_t; NULL = the null
  * stream). The context owns its device workspace (grown on demand, freed by bsvd_destroy) and a
  * pinned host staging buffer. Returns BSVD_OK or an error; *ctx is NULL on failure. */
@@ -119,6 +124,60 @@ int batched_svd(bsvd_ctx *ctx, int dtype, int batch, const int *m, const int *n,
  */
 int batched_qr(bsvd_ctx *ctx, int dtype, int batch, const int *m, const int *n, const void *const *A,
                const int *lda, void *const *Q, const int *ldq, void *const *R, const int *ldr);
+
+/*
+ * batched_rsvd -- truncated SVD A_b ~= U_b diag(S_b) V_b^T of every instance by the two-phase
+ * randomized method of Section 7.1 (Algorithm 4): Y = A Omega with a Gaussian Omega, Q = qr(Y),
+ * B = Q^T A, [Q_B, R_B] = qr(B^T), [U_R, S, V_R] = svd(R_B^T) by one-sided Jacobi, U = Q U_R,
+ * V = Q_B V_R, truncated to the smallest rank k whose discarded Frobenius mass satisfies
+ * ||A - U S V^T||_F <= eps ||A||_F (the relative Frobenius threshold of Section 8.2).
+ *
+ * The number of samples is found adaptively (the paper defers robust range finders to Halko,
+ * Martinsson, Tropp 2011): starting from ell0[b] samples (or none), blocks of 8 Gaussian samples are
+ * drawn, projected against the current basis twice (classical Gram-Schmidt), and the mean squared
+ * norm of the projected samples -- an unbiased estimate of ||(I - Q Q^T) A||_F^2 -- stops the
+ * growth once it is <= (eps / 2)^2 ||A||_F^2; the orthonormalised block is always appended. The exact
+ * test ||A||_F^2 - ||Q^T A||_F^2 <= eps^2 ||A||_F^2 then accepts the basis or resumes growth. The
+ * basis is capped at min(m, n, 64) columns.
+ *
+ * Omega's entry (row r, column j) of instance b is N(0,1) from Philox4x32-10 with counter
+ * (r, j, b, 0) and key (seed low, seed high), mapped by Box-Muller; column indices continue across
+ * blocks, so a run is reproducible from (seed, batch position).
+ *
+ *   batch        number of instances (0 does nothing)
+ *   m, n         host int[batch], 1 <= m, n <= 512
+ *   A, lda       host array of device pointers to FP64 inputs, lda >= m. Not modified.
+ *   eps          nullable host double[batch], 0 < eps < 1 (NULL: 1e-6). eps^2 must be well above
+ *                the FP64 rounding of ||A||_F^2 (eps >~ 1e-7).
+ *   max_rank     host int[batch] >= 1: capacity of S, U, V; a larger exact rank is truncated to it
+ *                and sets info = 2
+ *   S            host array of device pointers: the first rank[b] entries receive sigma, descending
+ *   U, ldu       nullable; U[b] (nullable entry) receives m x rank[b] left vectors, ldu >= m
+ *   V, ldv       nullable; V[b] (nullable entry) receives n x rank[b] right vectors, ldv >= n
+ *   rank         nullable DEVICE int[batch]: the chosen rank k
+ *   err_est      nullable DEVICE double[batch]: sqrt(discarded mass / ||A||_F^2), the relative
+ *                Frobenius error of the returned factors up to rounding
+ *   info         nullable DEVICE int[batch]: 0, 1 (Jacobi sweep cap), 2 (tolerance not met within
+ *                the basis cap, or rank > max_rank), 3 (non-finite input; rank 0)
+ *   seed         64-bit key of the sampling matrix
+ *   flags        BSVD_RSVD_* (0 = adaptive)
+ *   ell0         nullable host int[batch]: initial number of samples (clamped to the basis cap)
+ * The call synchronises its stream once per growth round and once per check (the per-instance
+ * decisions are read back to plan the next round). Returns BSVD_OK, BSVD_EARG, BSVD_EUNSUP,
+ * BSVD_ENOMEM or BSVD_EHIP.
+ */
+int batched_rsvd(bsvd_ctx *ctx, int batch, const int *m, const int *n, const void *const *A, const int *lda,
+                 const double *eps, const int *max_rank, void *const *S, void *const *U, const int *ldu,
+                 void *const *V, const int *ldv, int *rank, double *err_est, int *info, unsigned long long seed,
+                 unsigned flags, const int *ell0);
+
+/*
+ * bsvd_sample_omega -- write columns col0 .. col0+b-1 of instance `inst`'s Gaussian sampling matrix
+ * (the Omega of Section 7.1 as batched_rsvd draws it: Philox4x32-10 counter (row, column, inst, 0),
+ * key = seed, Box-Muller) into `out`, a DEVICE array of n x b doubles stored row-major
+ * (out[r * b + j] = Omega(r, col0 + j)). Enqueued on the context's stream.
+ */
+int bsvd_sample_omega(bsvd_ctx *ctx, unsigned long long seed, int inst, int n, int col0, int b, double *out);
 
 #ifdef __cplusplus
 }

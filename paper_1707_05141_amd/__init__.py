@@ -14,7 +14,8 @@ import torch
 from . import _lib
 from ._lib import BSVD_F32, BSVD_F64, BsvdError  # noqa: F401
 
-__all__ = ["batched_svd", "batched_qr", "svd", "qr", "colmajor", "from_colmajor", "BsvdError"]
+__all__ = ["batched_svd", "batched_qr", "batched_rsvd", "svd", "qr", "rsvd_packed", "pack_colmajor", "colmajor",
+           "from_colmajor", "BsvdError"]
 
 
 def _dtype_code(dt):
@@ -83,6 +84,43 @@ def batched_qr(m, n, A_ptrs, lda, Q_ptrs=None, ldq=None, R_ptrs=None, ldr=None, 
     ctx.check(rc)
 
 
+def batched_rsvd(m, n, A_ptrs, lda, max_rank, S_ptrs, U_ptrs=None, ldu=None, V_ptrs=None, ldv=None, *, eps=None,
+                 rank=None, err_est=None, info=None, seed=0, flags=0, ell0=None, device=None):
+    """Direct mirror of the C entry point ``batched_rsvd`` (host shape / eps / max_rank / ell0 arrays,
+    host arrays of device pointers, device tensors for rank / err_est / info)."""
+    L = _lib.lib()
+    ctx = _ctx(device if device is not None else torch.cuda.current_device())
+    m = _lib.i32(m)
+    n = _lib.i32(n)
+    batch = len(m)
+    A_ptrs = _lib.ptrs(A_ptrs)
+    lda = _lib.i32(lda)
+    max_rank = _lib.i32(max_rank)
+    S_ptrs = _lib.ptrs(S_ptrs)
+    U_ptrs = None if U_ptrs is None else _lib.ptrs(U_ptrs)
+    V_ptrs = None if V_ptrs is None else _lib.ptrs(V_ptrs)
+    ldu = None if ldu is None else _lib.i32(ldu)
+    ldv = None if ldv is None else _lib.i32(ldv)
+    eps = None if eps is None else np.ascontiguousarray(np.asarray(eps, dtype=np.float64))
+    ell0 = None if ell0 is None else _lib.i32(ell0)
+    rc = L.batched_rsvd(ctx.h, batch, _lib.as_ip(m), _lib.as_ip(n), _lib.as_vp(A_ptrs), _lib.as_ip(lda), _lib.as_dp(eps),
+                        _lib.as_ip(max_rank), _lib.as_vp(S_ptrs), _lib.as_vp(U_ptrs), _lib.as_ip(ldu),
+                        _lib.as_vp(V_ptrs), _lib.as_ip(ldv), None if rank is None else ctypes_ptr(rank),
+                        None if err_est is None else ctypes_ptr(err_est), None if info is None else ctypes_ptr(info),
+                        int(seed) & (2 ** 64 - 1), int(flags), _lib.as_ip(ell0))
+    ctx.check(rc)
+
+
+def sample_omega(seed, inst, n, col0, b, device=None):
+    """Columns col0 .. col0+b-1 of instance ``inst``'s sampling matrix as an n x b tensor."""
+    dev = torch.device(device if device is not None else "cuda")
+    out = torch.empty((n, b), dtype=torch.float64, device=dev)
+    ctx = _ctx(dev)
+    ctx.check(_lib.lib().bsvd_sample_omega(ctx.h, int(seed) & (2 ** 64 - 1), int(inst), int(n), int(col0), int(b),
+                                          ctypes_ptr(out)))
+    return out
+
+
 def ctypes_ptr(t: torch.Tensor):
     import ctypes
     return ctypes.c_void_p(t.data_ptr())
@@ -136,3 +174,48 @@ def qr(A: torch.Tensor, *, want_q=True, want_r=True):
                    _strided_ptrs(Rs, b) if want_r else None, np.full(b, k) if want_r else None,
                    dtype=dt, device=A.device)
     return (from_colmajor(Qs) if want_q else None), (from_colmajor(Rs) if want_r else None)
+
+
+def pack_colmajor(mats, device="cuda", dtype=torch.float64):
+    """Pack a list of 2-D numpy arrays into one device buffer, each instance column-major and
+    256-byte aligned. Returns (buffer, element offsets, m, n)."""
+    m = np.array([a.shape[0] for a in mats], dtype=np.int64)
+    n = np.array([a.shape[1] for a in mats], dtype=np.int64)
+    sizes = m * n
+    align = 32  # elements (256 bytes of FP64)
+    padded = (sizes + align - 1) // align * align
+    offs = np.concatenate([[0], np.cumsum(padded)[:-1]]).astype(np.int64)
+    host = np.zeros(int(padded.sum()) if len(mats) else 0, dtype=np.float64)
+    for a, o in zip(mats, offs):
+        host[o:o + a.size] = np.asarray(a, dtype=np.float64).ravel(order="F")
+    buf = torch.from_numpy(host).to(device=device, dtype=dtype)
+    return buf, offs, m.astype(np.int32), n.astype(np.int32)
+
+
+def rsvd_packed(buf, offs, m, n, *, eps=1e-6, max_rank=64, seed=0, flags=0, ell0=None, want_vectors=True):
+    """Randomized SVD of a packed uneven batch (see ``pack_colmajor``). Returns a dict with device
+    tensors: S [b, max_rank], U (packed, m_b x max_rank each), V (packed), rank, err_est, info, and the
+    element offsets of U / V instances."""
+    b = len(m)
+    dev = buf.device
+    es = buf.element_size()
+    maxr = np.broadcast_to(np.asarray(max_rank, dtype=np.int64), (b,)).astype(np.int32)
+    eps_a = np.broadcast_to(np.asarray(eps, dtype=np.float64), (b,)).copy()
+    S = torch.zeros((b, int(maxr.max()) if b else 1), dtype=torch.float64, device=dev)
+    u_sz = np.asarray(m, np.int64) * maxr
+    v_sz = np.asarray(n, np.int64) * maxr
+    u_off = np.concatenate([[0], np.cumsum(u_sz)[:-1]]).astype(np.int64) if b else np.zeros(0, np.int64)
+    v_off = np.concatenate([[0], np.cumsum(v_sz)[:-1]]).astype(np.int64) if b else np.zeros(0, np.int64)
+    U = torch.zeros(int(u_sz.sum()) if want_vectors and b else 1, dtype=torch.float64, device=dev)
+    V = torch.zeros(int(v_sz.sum()) if want_vectors and b else 1, dtype=torch.float64, device=dev)
+    rank = torch.zeros(b, dtype=torch.int32, device=dev)
+    err = torch.zeros(b, dtype=torch.float64, device=dev)
+    info = torch.zeros(b, dtype=torch.int32, device=dev)
+    if b:
+        A_ptrs = buf.data_ptr() + es * offs.astype(np.uint64)
+        S_ptrs = S.data_ptr() + 8 * S.shape[1] * np.arange(b, dtype=np.uint64)
+        batched_rsvd(m, n, A_ptrs, m, maxr, S_ptrs,
+                     (U.data_ptr() + 8 * u_off.astype(np.uint64)) if want_vectors else None, m if want_vectors else None,
+                     (V.data_ptr() + 8 * v_off.astype(np.uint64)) if want_vectors else None, n if want_vectors else None,
+                     eps=eps_a, rank=rank, err_est=err, info=info, seed=seed, flags=flags, ell0=ell0, device=dev)
+    return dict(S=S, U=U, V=V, u_off=u_off, v_off=v_off, rank=rank, err_est=err, info=info, max_rank=maxr)

@@ -23,10 +23,13 @@ SVD_QR_FIRST = 1 << 3
 SVD_NO_QR = 1 << 4
 SVD_JACOBI_ON_R = 1 << 5
 
+RSVD_FIXED = 1 << 0
+
 _lib = None
 
 _vp = ctypes.c_void_p
 _ip = ctypes.POINTER(ctypes.c_int)
+_dp = ctypes.POINTER(ctypes.c_double)
 
 
 class BsvdError(RuntimeError):
@@ -52,13 +55,17 @@ def lib():
     L.batched_svd.argtypes = [_vp, ctypes.c_int, ctypes.c_int, _ip, _ip, _vp, _ip, _vp, _vp, _ip, _vp, _ip,
                               ctypes.c_double, ctypes.c_int, _vp, _vp, ctypes.c_uint]
     L.batched_qr.argtypes = [_vp, ctypes.c_int, ctypes.c_int, _ip, _ip, _vp, _ip, _vp, _ip, _vp, _ip]
+    L.batched_rsvd.argtypes = [_vp, ctypes.c_int, _ip, _ip, _vp, _ip, _dp, _ip, _vp, _vp, _ip, _vp, _ip, _vp, _vp, _vp,
+                               ctypes.c_ulonglong, ctypes.c_uint, _ip]
+    L.bsvd_sample_omega.argtypes = [_vp, ctypes.c_ulonglong, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                    _vp]
     _lib = L
     return L
 
 
 def exported_symbols():
     return ["bsvd_create", "bsvd_destroy", "bsvd_last_error", "bsvd_sync", "bsvd_version", "batched_svd",
-            "batched_qr"]
+            "batched_qr", "batched_rsvd", "bsvd_sample_omega"]
 
 
 def i32(a):
@@ -71,6 +78,10 @@ def ptrs(a):
 
 def as_ip(a):
     return None if a is None else a.ctypes.data_as(_ip)
+
+
+def as_dp(a):
+    return None if a is None else a.ctypes.data_as(_dp)
 
 
 def as_vp(a):

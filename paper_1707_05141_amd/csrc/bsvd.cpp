@@ -12,66 +12,9 @@
 
 #include "common.hpp"
 #include "ctx.hpp"
+#include "plan.hpp"
 
 using namespace bsvd;
-
-namespace {
-
-// Bump allocator for laying out one call's workspace (256-byte aligned blocks).
-struct Arena {
-    size_t off = 0;
-    size_t alloc(size_t bytes, size_t align = 256) {
-        off = (off + align - 1) & ~(align - 1);
-        const size_t r = off;
-        off += bytes;
-        return r;
-    }
-};
-
-enum { JK_WAVE = 0, JK_LDS = 1 };
-
-struct JKey {
-    int kind = 0, a = 0, b = 0;
-    bool operator<(const JKey &o) const {
-        if (kind != o.kind) return kind < o.kind;
-        if (a != o.a) return a < o.a;
-        return b < o.b;
-    }
-};
-
-struct QKey {
-    int nb = 0, seg = 0, kr = 0;
-    bool operator<(const QKey &o) const {
-        if (nb != o.nb) return nb < o.nb;
-        if (seg != o.seg) return seg < o.seg;
-        return kr < o.kr;
-    }
-};
-
-// Kernel choice for an M x N working matrix (M >= N): the wavefront-resident kernel when the
-// matrix and its V fit one wave's registers, else the LDS-resident kernel.
-int choose_jacobi(int dtype, int M, int N, unsigned flags, JKey *key) {
-    int a = 0, b = 0;
-    const bool wave_ok = jacobi_wave_supported(dtype, M, N, &a, &b);
-    int la = 0, lb = 0;
-    const bool lds_ok = jacobi_lds_supported(dtype, M, N, &la, &lb);
-    if (flags & BSVD_SVD_FORCE_WAVE) {
-        if (!wave_ok) return BSVD_EUNSUP;
-        *key = JKey{JK_WAVE, a, b};
-    } else if (flags & BSVD_SVD_FORCE_LDS) {
-        if (!lds_ok) return BSVD_EUNSUP;
-        *key = JKey{JK_LDS, la, lb};
-    } else if (wave_ok) {
-        *key = JKey{JK_WAVE, a, b};
-    } else if (lds_ok) {
-        *key = JKey{JK_LDS, la, lb};
-    } else {
-        return BSVD_EUNSUP;
-    }
-    return BSVD_OK;
-}
-
-}  // namespace
 
 namespace bsvd {
 
@@ -127,9 +70,26 @@ int Ctx::ensure_host(size_t bytes) {
     return BSVD_OK;
 }
 
-int Ctx::upload(size_t bytes) {
+int Ctx::upload(size_t bytes) { return upload_to(0, bytes); }
+
+int Ctx::ensure_readback(size_t bytes) {
+    if (bytes <= rb_size) return BSVD_OK;
+    if (rb) hipHostFree(rb);
+    rb = nullptr;
+    rb_size = 0;
+    size_t want = bytes + bytes / 4 + 4096;
+    hipError_t e = hipHostMalloc(&rb, want, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(BSVD_ENOMEM, "pinned readback buffer of %zu bytes: %s", want, hipGetErrorString(e));
+    }
+    rb_size = want;
+    return BSVD_OK;
+}
+
+int Ctx::upload_to(size_t dst_off, size_t bytes) {
     if (bytes == 0) return BSVD_OK;
-    hipError_t e = hipMemcpyAsync(dws, hws, bytes, hipMemcpyHostToDevice, stream);
+    hipError_t e = hipMemcpyAsync(static_cast<char *>(dws) + dst_off, hws, bytes, hipMemcpyHostToDevice, stream);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(descriptors)");
     e = hipEventRecord(staged, stream);
     if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
@@ -167,6 +127,7 @@ void bsvd_destroy(bsvd_ctx *ctx) {
     hipStreamSynchronize(c->stream);
     if (c->dws) hipFree(c->dws);
     if (c->hws) hipHostFree(c->hws);
+    if (c->rb) hipHostFree(c->rb);
     hipEventDestroy(c->staged);
     delete c;
 }

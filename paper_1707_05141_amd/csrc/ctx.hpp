@@ -26,6 +26,12 @@ struct Ctx {
     int ensure_host(size_t bytes);
     // Copy the first `bytes` of the staging buffer to the start of the device workspace.
     int upload(size_t bytes);
+    // Copy the first `bytes` of the staging buffer to device workspace offset `dst_off`.
+    int upload_to(size_t dst_off, size_t bytes);
+    // Pinned host buffer for small device -> host readbacks.
+    void *rb = nullptr;
+    size_t rb_size = 0;
+    int ensure_readback(size_t bytes);
 };
 
 }  // namespace bsvd

@@ -1,0 +1,369 @@
+// Device kernels of the batched randomized SVD (Section 7.1, Algorithm 4) with an adaptive range
+// finder and an a-posteriori error check.
+//
+//   rng_kernel       Gaussian sampling matrix Omega (n x b per instance), counter-based Philox4x32-10
+//                    (Salmon, Moraes, Dror, Shaw, SC'11) mapped to N(0, 1) by Box-Muller; entry
+//                    (row, col) of instance inst uses counter (row, col, inst, 0) and key = seed.
+//   gemm_nn_kernel   C = alpha X Y + beta C for a tall X (sketch Y = A Omega, CGS projections
+//                    Y_b -= Q H, back-transforms U = Q U_R): one lane per row of X, the small Y
+//                    staged in LDS, every element of X read once. Optional per-tile partial sums of
+//                    X^2 (||A||_F^2) and of the outputs' squares.
+//   gemm_tn_kernel   C = X^T Y with the reduction over the tall dimension (B^T = A^T Q, H = Q^T Y_b):
+//                    one lane per column of X, row chunks of Y staged in LDS. Optional partial sum of
+//                    the outputs' squares (||B||_F^2).
+//   small kernels    per-instance decisions: finishing ||A||_F^2, the growth test, the exact check
+//                    ||A||_F^2 - ||Q^T A||_F^2 <= eps^2 ||A||_F^2, the truncation rule and outputs.
+// Partial sums are written per tile and reduced in a fixed order, so results are bitwise
+// reproducible run to run.
+
+#include "common.hpp"
+#include "rsvd.hpp"
+
+namespace bsvd {
+
+// ---------------------------------------------------------------------------------------------
+// Philox4x32-10 and Box-Muller
+// ---------------------------------------------------------------------------------------------
+__device__ __forceinline__ void philox_rounds(uint32_t &x0, uint32_t &x1, uint32_t &x2, uint32_t &x3, uint32_t k0,
+                                              uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t lo0 = 0xD2511F53u * x0;
+        const uint32_t hi0 = __umulhi(0xD2511F53u, x0);
+        const uint32_t lo1 = 0xCD9E8D57u * x2;
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, x2);
+        const uint32_t y0 = hi1 ^ x1 ^ k0;
+        const uint32_t y2 = hi0 ^ x3 ^ k1;
+        x0 = y0;
+        x1 = lo1;
+        x2 = y2;
+        x3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+}
+
+__device__ __forceinline__ double gauss_entry(unsigned long long seed, uint32_t inst, uint32_t col, uint32_t row) {
+    uint32_t x0 = row, x1 = col, x2 = inst, x3 = 0u;
+    philox_rounds(x0, x1, x2, x3, (uint32_t)seed, (uint32_t)(seed >> 32));
+    const unsigned long long a = ((((unsigned long long)x0) << 32) | x1) >> 11;
+    const unsigned long long b = ((((unsigned long long)x2) << 32) | x3) >> 11;
+    const double u1 = ((double)a + 0.5) * 0x1.0p-53;
+    const double u2 = ((double)b + 0.5) * 0x1.0p-53;
+    return sqrt(-2.0 * log(u1)) * cos(6.283185307179586476925286766559 * u2);
+}
+
+// Omega block: rows 0..n-1, columns col0 .. col0+b-1, stored row-major (n x b, leading dim ld).
+__global__ __launch_bounds__(256) void rng_kernel(const RngDesc *__restrict__ d, const int2 *__restrict__ tiles,
+                                                  unsigned long long seed) {
+    const int2 tl = tiles[blockIdx.x];
+    const RngDesc D = d[tl.x];
+    const int idx = tl.y * 256 + threadIdx.x;
+    const int r = idx / D.b, j = idx - (idx / D.b) * D.b;
+    if (r >= D.n) return;
+    D.out[(size_t)r * D.ld + j] = gauss_entry(seed, (uint32_t)D.inst, (uint32_t)(D.col0 + j), (uint32_t)r);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// ---------------------------------------------------------------------------------------------
+// C (M x N) = alpha X (M x K) Y (K x N) + beta C. X, C column-major; Y column-major (ytrans = 0)
+// or row-major (ytrans = 1, element (k, j) at Y[k * ldy + j]). One 64-lane workgroup per 64-row
+// tile; N <= NMAX.
+// ---------------------------------------------------------------------------------------------
+template <int NMAX>
+__global__ __launch_bounds__(64) void gemm_nn_kernel(const MMDesc *__restrict__ d, const int2 *__restrict__ tiles) {
+    constexpr int KC = 64;
+    __shared__ double ys[KC * NMAX];
+    const int2 tl = tiles[blockIdx.x];
+    const MMDesc D = d[tl.x];
+    const int lane = threadIdx.x;
+    const int r = tl.y * 64 + lane;
+    const bool rok = r < D.M;
+    double acc[NMAX];
+#pragma unroll
+    for (int j = 0; j < NMAX; ++j) acc[j] = 0.0;
+    double xs = 0.0;
+    for (int k0 = 0; k0 < D.K; k0 += KC) {
+        const int kc = (D.K - k0) < KC ? (D.K - k0) : KC;
+        for (int idx = lane; idx < kc * NMAX; idx += 64) {
+            const int kk = idx / NMAX, j = idx - (idx / NMAX) * NMAX;
+            double y = 0.0;
+            if (j < D.N) y = D.ytrans ? D.Y[(size_t)(k0 + kk) * D.ldy + j] : D.Y[(k0 + kk) + (size_t)j * D.ldy];
+            ys[idx] = y;
+        }
+        __syncthreads();
+        if (rok) {
+            const double *xp = D.X + r + (size_t)k0 * D.ldx;
+            int kk = 0;
+            for (; kk + 4 <= kc; kk += 4) {
+                const double x0 = xp[(size_t)(kk + 0) * D.ldx];
+                const double x1 = xp[(size_t)(kk + 1) * D.ldx];
+                const double x2 = xp[(size_t)(kk + 2) * D.ldx];
+                const double x3 = xp[(size_t)(kk + 3) * D.ldx];
+                xs = fma(x0, x0, xs);
+                xs = fma(x1, x1, xs);
+                xs = fma(x2, x2, xs);
+                xs = fma(x3, x3, xs);
+#pragma unroll
+                for (int j = 0; j < NMAX; ++j) {
+                    acc[j] = fma(x0, ys[(kk + 0) * NMAX + j], acc[j]);
+                    acc[j] = fma(x1, ys[(kk + 1) * NMAX + j], acc[j]);
+                    acc[j] = fma(x2, ys[(kk + 2) * NMAX + j], acc[j]);
+                    acc[j] = fma(x3, ys[(kk + 3) * NMAX + j], acc[j]);
+                }
+            }
+            for (; kk < kc; ++kk) {
+                const double x = xp[(size_t)kk * D.ldx];
+                xs = fma(x, x, xs);
+#pragma unroll
+                for (int j = 0; j < NMAX; ++j) acc[j] = fma(x, ys[kk * NMAX + j], acc[j]);
+            }
+        }
+        __syncthreads();
+    }
+    double cs = 0.0;
+    if (rok) {
+#pragma unroll
+        for (int j = 0; j < NMAX; ++j) {
+            if (j < D.N) {
+                double* cp = D.C + r + (size_t)j * D.ldc;
+                const double v = D.beta != 0.0 ? fma(D.alpha, acc[j], D.beta * (*cp)) : D.alpha * acc[j];
+                *cp = v;
+                cs = fma(v, v, cs);
+            }
+        }
+    }
+    if (D.xsq) {
+        xs = wave_sum(xs);
+        if (lane == 0) D.xsq[tl.y] = xs;
+    }
+    if (D.csq) {
+        cs = wave_sum(cs);
+        if (lane == 0) D.csq[tl.y] = cs;
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// C (K x N) = X^T Y, X column-major M x K, Y column-major M x N, C column-major K x N.
+// One 64-lane workgroup per 64 columns of X; N <= NMAX.
+// ---------------------------------------------------------------------------------------------
+template <int NMAX>
+__global__ __launch_bounds__(64) void gemm_tn_kernel(const MMDesc *__restrict__ d, const int2 *__restrict__ tiles) {
+    constexpr int RC = 32;
+    __shared__ double ys[RC * NMAX];
+    const int2 tl = tiles[blockIdx.x];
+    const MMDesc D = d[tl.x];
+    const int lane = threadIdx.x;
+    const int c = tl.y * 64 + lane;
+    const bool cok = c < D.K;
+    double acc[NMAX];
+#pragma unroll
+    for (int j = 0; j < NMAX; ++j) acc[j] = 0.0;
+    for (int r0 = 0; r0 < D.M; r0 += RC) {
+        const int rc = (D.M - r0) < RC ? (D.M - r0) : RC;
+        for (int idx = lane; idx < RC * NMAX; idx += 64) {
+            const int j = idx / RC, rr = idx - (idx / RC) * RC;
+            double y = 0.0;
+            if (j < D.N && rr < rc) y = D.Y[(r0 + rr) + (size_t)j * D.ldy];
+            ys[rr * NMAX + j] = y;
+        }
+        __syncthreads();
+        if (cok) {
+            const double *xp = D.X + r0 + (size_t)c * D.ldx;
+            for (int rr = 0; rr < rc; ++rr) {
+                const double x = xp[rr];
+#pragma unroll
+                for (int j = 0; j < NMAX; ++j) acc[j] = fma(x, ys[rr * NMAX + j], acc[j]);
+            }
+        }
+        __syncthreads();
+    }
+    double cs = 0.0;
+    if (cok) {
+#pragma unroll
+        for (int j = 0; j < NMAX; ++j) {
+            if (j < D.N) {
+                D.C[c + (size_t)j * D.ldc] = acc[j];
+                cs = fma(acc[j], acc[j], cs);
+            }
+        }
+    }
+    if (D.csq) {
+        cs = wave_sum(cs);
+        if (lane == 0) D.csq[tl.y] = cs;
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Per-instance decisions (one thread per instance in the launch list).
+// ---------------------------------------------------------------------------------------------
+
+// After a growth block of b columns: finish ||A||_F^2 on the first pass (a non-finite sum marks
+// the instance), form the estimator est2 = ||Y_b||_F^2 / b and decide whether growth stops.
+__global__ void grow_decide_kernel(RsvdState *__restrict__ st, const GrowItem *__restrict__ items, int count,
+                                   int *__restrict__ flags) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= count) return;
+    const GrowItem it = items[t];
+    RsvdState &S = st[it.inst];
+    if (it.first) {
+        double a = 0.0;
+        for (int i = 0; i < S.ntile_m; ++i) a += S.xsq[i];
+        S.normA2 = a;
+        S.nonfinite = __builtin_isfinite(a) ? 0 : 1;
+    }
+    double e = 0.0;
+    for (int i = 0; i < S.ntile_m; ++i) e += S.csq[i];
+    const double est2 = e / (double)it.b;
+    const double thr = (S.eps / S.safety) * (S.eps / S.safety) * S.normA2;
+    S.ell += it.b;
+    S.flag = (S.nonfinite || est2 <= thr || S.ell >= S.cap) ? 1 : 0;
+    flags[t] = S.flag;
+}
+
+// After an initial block of b samples: finish ||A||_F^2.
+__global__ void init_norm_kernel(RsvdState *__restrict__ st, const GrowItem *__restrict__ items, int count) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= count) return;
+    const GrowItem it = items[t];
+    RsvdState &S = st[it.inst];
+    double a = 0.0;
+    for (int i = 0; i < S.ntile_m; ++i) a += S.xsq[i];
+    S.normA2 = a;
+    S.nonfinite = __builtin_isfinite(a) ? 0 : 1;
+    S.ell = it.b;
+}
+
+// Exact check ||A - Q Q^T A||_F^2 = ||A||_F^2 - ||B||_F^2 <= eps^2 ||A||_F^2.
+__global__ void check_kernel(RsvdState *__restrict__ st, const int *__restrict__ list, int count,
+                             int *__restrict__ flags) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= count) return;
+    RsvdState &S = st[list[t]];
+    double b2 = 0.0;
+    for (int i = 0; i < S.ntile_n; ++i) b2 += S.bsq[i];
+    S.check_ok = (S.normA2 - b2) <= S.eps * S.eps * S.normA2 ? 1 : 0;
+    S.flag = S.check_ok | S.nonfinite;
+    flags[t] = S.flag;
+}
+
+// Truncation (Section 8.2): smallest k with resid2 + sum_{i>=k} sigma_i^2 <= eps^2 ||A||_F^2,
+// resid2 = max(0, ||A||_F^2 - sum_i sigma_i^2), tails summed from the smallest sigma upward; then
+// the outputs S[:k], rank, error estimate and info.
+__global__ void finalize_kernel(RsvdState *__restrict__ st, const int *__restrict__ list, int count,
+                                int *__restrict__ rank_out, double *__restrict__ err_out, int *__restrict__ info_out,
+                                const int *__restrict__ jinfo, int *__restrict__ rank_copy) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= count) return;
+    const int inst = list[t];
+    RsvdState &S = st[inst];
+    const int ell = S.ell;
+    const double *sg = S.sig;
+    const double normA2 = S.normA2;
+    double tot = 0.0;
+    for (int i = ell - 1; i >= 0; --i) tot += sg[i] * sg[i];
+    double resid2 = normA2 - tot;
+    if (resid2 < 0.0) resid2 = 0.0;
+    const double thr = S.eps * S.eps * normA2;
+    double tail = resid2, tail_at_k = resid2;
+    int k = ell;
+    if (tail <= thr) {
+        for (int i = ell - 1; i >= 0; --i) {
+            const double t2 = tail + sg[i] * sg[i];
+            if (t2 <= thr) {
+                tail = t2;
+                k = i;
+                tail_at_k = t2;
+            } else {
+                break;
+            }
+        }
+    }
+    int info = jinfo ? (jinfo[t] == INFO_SWEEPS ? INFO_SWEEPS : INFO_OK) : INFO_OK;
+    const int kk = k < S.max_rank ? k : S.max_rank;
+    if (k > S.max_rank) info = INFO_RANKCAP;
+    double terr;
+    if (kk < k) {
+        double dropped = 0.0;
+        for (int i = ell - 1; i >= kk; --i) dropped += sg[i] * sg[i];
+        terr = resid2 + dropped;
+    } else {
+        terr = tail_at_k;
+    }
+    if (info == INFO_OK && !S.check_ok) info = INFO_RANKCAP;
+    if (S.nonfinite) info = INFO_NONFINITE;
+    S.rank = S.nonfinite ? 0 : kk;
+    for (int i = 0; i < kk && !S.nonfinite; ++i) S.Sout[i] = sg[i];
+    if (rank_out) rank_out[inst] = S.rank;
+    rank_copy[t] = S.rank;
+    if (err_out) err_out[inst] = normA2 > 0.0 ? sqrt(terr / normA2) : 0.0;
+    if (info_out) info_out[inst] = info;
+}
+
+// ---------------------------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------------------------
+hipError_t launch_rng(const RngDesc *d, const int2 *tiles, int ntiles, unsigned long long seed, hipStream_t st) {
+    if (ntiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(rng_kernel, dim3(ntiles), dim3(256), 0, st, d, tiles, seed);
+    return hipGetLastError();
+}
+
+hipError_t launch_gemm_nn(int nmax, const MMDesc *d, const int2 *tiles, int ntiles, hipStream_t st) {
+    if (ntiles <= 0) return hipSuccess;
+    switch (nmax) {
+        case 8: hipLaunchKernelGGL(gemm_nn_kernel<8>, dim3(ntiles), dim3(64), 0, st, d, tiles); break;
+        case 16: hipLaunchKernelGGL(gemm_nn_kernel<16>, dim3(ntiles), dim3(64), 0, st, d, tiles); break;
+        case 32: hipLaunchKernelGGL(gemm_nn_kernel<32>, dim3(ntiles), dim3(64), 0, st, d, tiles); break;
+        case 64: hipLaunchKernelGGL(gemm_nn_kernel<64>, dim3(ntiles), dim3(64), 0, st, d, tiles); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_gemm_tn(int nmax, const MMDesc *d, const int2 *tiles, int ntiles, hipStream_t st) {
+    if (ntiles <= 0) return hipSuccess;
+    switch (nmax) {
+        case 8: hipLaunchKernelGGL(gemm_tn_kernel<8>, dim3(ntiles), dim3(64), 0, st, d, tiles); break;
+        case 16: hipLaunchKernelGGL(gemm_tn_kernel<16>, dim3(ntiles), dim3(64), 0, st, d, tiles); break;
+        case 32: hipLaunchKernelGGL(gemm_tn_kernel<32>, dim3(ntiles), dim3(64), 0, st, d, tiles); break;
+        case 64: hipLaunchKernelGGL(gemm_tn_kernel<64>, dim3(ntiles), dim3(64), 0, st, d, tiles); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+static inline int nblk(int n, int b) { return (n + b - 1) / b; }
+
+hipError_t launch_grow_decide(RsvdState *st, const GrowItem *items, int count, int *flags, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(grow_decide_kernel, dim3(nblk(count, 256)), dim3(256), 0, s, st, items, count, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_norm(RsvdState *st, const GrowItem *items, int count, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(init_norm_kernel, dim3(nblk(count, 256)), dim3(256), 0, s, st, items, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_check(RsvdState *st, const int *list, int count, int *flags, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(check_kernel, dim3(nblk(count, 256)), dim3(256), 0, s, st, list, count, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(RsvdState *st, const int *list, int count, int *rank, double *err, int *info,
+                           const int *jinfo, int *rank_copy, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(finalize_kernel, dim3(nblk(count, 256)), dim3(256), 0, s, st, list, count, rank, err, info,
+                       jinfo, rank_copy);
+    return hipGetLastError();
+}
+
+}  // namespace bsvd

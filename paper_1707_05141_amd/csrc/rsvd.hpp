@@ -1,0 +1,51 @@
+// Descriptors and launchers of the batched randomized SVD kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace bsvd {
+
+// Omega block of one instance: n rows, b columns starting at counter column col0, row-major.
+struct RngDesc {
+    double *out;
+    int n, b, col0, ld, inst;
+};
+
+// One GEMM of the pipeline (see rsvd.hip for the two shapes).
+struct MMDesc {
+    const double *X;
+    const double *Y;
+    double *C;
+    double *xsq;  // nullable: per-tile partial sums of X^2 (gemm_nn only)
+    double *csq;  // nullable: per-tile partial sums of the outputs' squares
+    double alpha, beta;
+    int M, N, K, ldx, ldy, ldc, ytrans;
+};
+
+// Device-resident state of one randomized-SVD instance.
+struct RsvdState {
+    const double *A;
+    double *xsq, *csq, *bsq;  // per-tile partial sums (row tiles of A, row tiles of A, column tiles of A)
+    double *sig;              // singular values of R_B^T (capacity cap)
+    double *Sout;             // caller's S
+    double normA2, eps, safety;
+    int m, n, lda, cap, ell, max_rank;
+    int ntile_m, ntile_n;
+    int flag, check_ok, nonfinite, rank;
+};
+
+// One entry of a growth round: instance, block size, first block flag.
+struct GrowItem {
+    int inst, b, first, pad;
+};
+
+hipError_t launch_rng(const RngDesc *d, const int2 *tiles, int ntiles, unsigned long long seed, hipStream_t st);
+hipError_t launch_gemm_nn(int nmax, const MMDesc *d, const int2 *tiles, int ntiles, hipStream_t st);
+hipError_t launch_gemm_tn(int nmax, const MMDesc *d, const int2 *tiles, int ntiles, hipStream_t st);
+hipError_t launch_grow_decide(RsvdState *st, const GrowItem *items, int count, int *flags, hipStream_t s);
+hipError_t launch_init_norm(RsvdState *st, const GrowItem *items, int count, hipStream_t s);
+hipError_t launch_check(RsvdState *st, const int *list, int count, int *flags, hipStream_t s);
+hipError_t launch_finalize(RsvdState *st, const int *list, int count, int *rank, double *err, int *info,
+                           const int *jinfo, int *rank_copy, hipStream_t s);
+
+}  // namespace bsvd
