@@ -171,7 +171,128 @@ def run_c2(args, torch, P, synth):
     return res
 
 
-WORKLOADS = {"c1": run_c1, "c2": run_c2}
+def _rsvd_buffers(torch, m, n, max_rank):
+    b = len(m)
+    maxr = np.full(b, max_rank, dtype=np.int32)
+    S = torch.zeros((b, max_rank), dtype=torch.float64, device="cuda")
+    u_off = np.concatenate([[0], np.cumsum(m.astype(np.int64) * max_rank)[:-1]]).astype(np.int64)
+    v_off = np.concatenate([[0], np.cumsum(n.astype(np.int64) * max_rank)[:-1]]).astype(np.int64)
+    U = torch.zeros(int((m.astype(np.int64) * max_rank).sum()), dtype=torch.float64, device="cuda")
+    V = torch.zeros(int((n.astype(np.int64) * max_rank).sum()), dtype=torch.float64, device="cuda")
+    rank = torch.zeros(b, dtype=torch.int32, device="cuda")
+    err = torch.zeros(b, dtype=torch.float64, device="cuda")
+    info = torch.zeros(b, dtype=torch.int32, device="cuda")
+    return dict(maxr=maxr, S=S, U=U, V=V, u_off=u_off, v_off=v_off, rank=rank, err=err, info=info)
+
+
+def run_c4(args, torch, P, synth):
+    """20,000 blocks a_ij = exp(-|x_i - y_j| / 0.1), m, n uniform on {64, 128, 256, 512}, x uniform in
+    [0,1]^2, y uniform in [2,3] x [0,1]; randomized SVD to relative Frobenius error 1e-6 (plain FP64,
+    adaptive range finder, exact check)."""
+    import oracle
+    count, dseed, oseed, eps, max_rank = 20000, 4, 12345, 1e-6, 64
+    m, n = synth.uneven_shapes(count, seed=dseed)
+    t0 = time.perf_counter()
+    buf, offs = synth.kernel_blocks_packed(m, n, seed=dseed, kind="exp")
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - t0
+    o = _rsvd_buffers(torch, m, n, max_rank)
+    A_ptrs = buf.data_ptr() + 8 * offs.astype(np.uint64)
+    S_ptrs = o["S"].data_ptr() + 8 * max_rank * np.arange(count, dtype=np.uint64)
+    U_ptrs = o["U"].data_ptr() + 8 * o["u_off"].astype(np.uint64)
+    V_ptrs = o["V"].data_ptr() + 8 * o["v_off"].astype(np.uint64)
+    eps_a = np.full(count, eps)
+
+    def step():
+        P.batched_rsvd(m, n, A_ptrs, m, o["maxr"], S_ptrs, U_ptrs, m, V_ptrs, n, eps=eps_a, rank=o["rank"],
+                       err_est=o["err"], info=o["info"], seed=oseed)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    P.profile_enable(True)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ev[i][0].record()
+        step()
+        ev[i][1].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prof = P.profile_read()
+    P.profile_enable(False)
+    ms_per_step = wall * 1e3 / args.steps
+    gpu_ms = float(np.mean([s.elapsed_time(e) for s, e in ev]))
+    info = o["info"].cpu().numpy()
+    rank = o["rank"].cpu().numpy()
+    err = o["err"].cpu().numpy()
+    assert np.all(info == 0), np.bincount(info)
+    assert err.max() <= eps
+    # parity spot check: oracle on sampled instances (the exact bytes the GPU factored)
+    rng = np.random.default_rng(1)
+    idx = rng.choice(count, 24, replace=False)
+    nbad = 0
+    for i in idx:
+        mi, ni = int(m[i]), int(n[i])
+        A = buf[int(offs[i]):int(offs[i]) + mi * ni].cpu().numpy().reshape(ni, mi).T
+        ref = oracle.rsvd_adaptive(A, seed=oseed, inst=int(i), eps=eps, blk=8, cap=min(mi, ni, 64), safety=2.0,
+                                   max_rank=max_rank)
+        k = int(rank[i])
+        Ug = o["U"][int(o["u_off"][i]):int(o["u_off"][i]) + mi * k].cpu().numpy().reshape(k, mi).T
+        Vg = o["V"][int(o["v_off"][i]):int(o["v_off"][i]) + ni * k].cpu().numpy().reshape(k, ni).T
+        Sg = o["S"][i, :k].cpu().numpy()
+        rel = np.linalg.norm(A - (Ug * Sg) @ Vg.T) / np.linalg.norm(A)
+        assert rel <= eps, (i, rel)
+        nbad += int(k != ref["rank"])
+    per = {k: v["ms"] / args.steps for k, v in prof.items()}
+    flops = sum(v["flops"] for v in prof.values()) / args.steps
+    dom = max(("sketch", "project", "cgs", "qr", "jacobi", "output"), key=lambda s: prof[s]["ms"])
+    dom_ms = prof[dom]["ms"] / max(1, prof[dom]["launches"])
+    dom_bytes = prof[dom]["bytes"] / max(1, prof[dom]["launches"])
+    achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
+    a_bytes = float((8 * m.astype(np.float64) * n).sum())
+    res = dict(value=count / (ms_per_step * 1e-3), unit="SVDs/s", ms_per_step=ms_per_step, dtype="f64",
+               config=dict(workload="rsvd_f64_adaptive_20000_exp_blocks_m_n_in_64_512", batch=count, eps=eps,
+                           max_rank=max_rank, precision="plain FP64", gflop_per_s=flops / (ms_per_step * 1e-3) / 1e9,
+                           gpu_event_ms_per_step=gpu_ms, stage_ms_per_step=per, input_GB=a_bytes / 1e9,
+                           passes_over_A=(prof["sketch"]["bytes"] + prof["project"]["bytes"]) / args.steps / a_bytes,
+                           mean_rank=float(rank.mean()), max_err_est=float(err.max()),
+                           sampled_rank_mismatch=nbad, generation_s=gen_s),
+               roofline=dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
+                             frac=achieved / HBM_PEAK_GBS, traffic=None, kernel="stage:" + dom,
+                             kernel_ms=dom_ms, bytes_per_launch=dom_bytes))
+    if args.cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline_rsvd(m, n, dseed, oseed, eps, max_rank, synth, oracle)
+    return res
+
+
+def cpu_baseline_rsvd(m, n, dseed, oseed, eps, max_rank, synth, oracle):
+    """The oracle's adaptive randomized SVD on a stratified sample (8 instances per (m, n) bin, the
+    first ones of each bin in the batch), threads across instances; SVDs/s of the sample."""
+    from concurrent.futures import ThreadPoolExecutor
+    picks = []
+    for mm in (64, 128, 256, 512):
+        for nn in (64, 128, 256, 512):
+            picks += [int(i) for i in np.nonzero((m == mm) & (n == nn))[0][:8]]
+    mats = [synth.kernel_block(int(m[i]), int(n[i]), dseed, i) for i in picks]
+    threads = os.cpu_count() or 1
+
+    def one(j):
+        i = picks[j]
+        A = mats[j]
+        return oracle.rsvd_adaptive(A, seed=oseed, inst=i, eps=eps, blk=8, cap=min(A.shape[0], A.shape[1], 64),
+                                    safety=2.0, max_rank=max_rank)["rank"]
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        list(ex.map(one, range(len(picks))))
+    dt = time.perf_counter() - t0
+    return dict(value=len(picks) / dt, unit="SVDs/s", cores=threads, kind="oracle",
+                sample="%d instances: the first 8 of each of the 16 (m, n) bins of the same batch, %.1f s wall"
+                       % (len(picks), dt))
+
+
+WORKLOADS = {"c1": run_c1, "c2": run_c2, "c4": run_c4}
 
 
 def main():

@@ -71,6 +71,28 @@ const char *bsvd_last_error(const bsvd_ctx *ctx);
 /* Block until all work enqueued by this context has finished. */
 int bsvd_sync(bsvd_ctx *ctx);
 
+/* Stages reported by the profiler. */
+enum {
+    BSVD_STAGE_RNG = 0,     /* Gaussian sampling matrix */
+    BSVD_STAGE_SKETCH = 1,  /* Y = A Omega (one pass over A) */
+    BSVD_STAGE_CGS = 2,     /* Gram-Schmidt projections of sample blocks */
+    BSVD_STAGE_QR = 3,      /* Householder QR (of A, of sample blocks, of B^T) */
+    BSVD_STAGE_PROJECT = 4, /* B^T = A^T Q (one pass over A) */
+    BSVD_STAGE_JACOBI = 5,  /* one-sided Jacobi SVD */
+    BSVD_STAGE_SMALL = 6,   /* per-instance decisions and truncation */
+    BSVD_STAGE_OUTPUT = 7,  /* back-transforms U = Q U_R, V = Q_B V_R */
+    BSVD_STAGE_COUNT = 8
+};
+
+/* Turn per-stage profiling on (1) or off (0) and clear previous records (synchronises the stream).
+ * While on, every launch group is bracketed by HIP events on the context's stream. */
+int bsvd_profile_enable(bsvd_ctx *ctx, int on);
+
+/* Synchronise, then sum the records since the last enable/read per stage: elapsed milliseconds,
+ * algorithmic bytes (inputs read once + outputs written once) and flops, and the number of
+ * launch groups; all output arrays have `nstage` entries (nullable). Clears the records. */
+int bsvd_profile_read(bsvd_ctx *ctx, int nstage, double *ms, double *bytes, double *flops, int *launches);
+
 /* Library version string. */
 const char *bsvd_version(void);
 

@@ -121,6 +121,25 @@ def sample_omega(seed, inst, n, col0, b, device=None):
     return out
 
 
+def profile_enable(on=True, device=None):
+    """Turn per-stage HIP-event profiling of library launches on or off (clears records)."""
+    ctx = _ctx(device if device is not None else torch.cuda.current_device())
+    ctx.check(_lib.lib().bsvd_profile_enable(ctx.h, 1 if on else 0))
+
+
+def profile_read(device=None):
+    """Per-stage sums since the last enable/read: {stage: dict(ms, bytes, flops, launches)}."""
+    ctx = _ctx(device if device is not None else torch.cuda.current_device())
+    ns = len(_lib.STAGES)
+    ms = np.zeros(ns)
+    by = np.zeros(ns)
+    fl = np.zeros(ns)
+    la = np.zeros(ns, dtype=np.int32)
+    ctx.check(_lib.lib().bsvd_profile_read(ctx.h, ns, _lib.as_dp(ms), _lib.as_dp(by), _lib.as_dp(fl), _lib.as_ip(la)))
+    return {name: dict(ms=float(ms[i]), bytes=float(by[i]), flops=float(fl[i]), launches=int(la[i]))
+            for i, name in enumerate(_lib.STAGES)}
+
+
 def ctypes_ptr(t: torch.Tensor):
     import ctypes
     return ctypes.c_void_p(t.data_ptr())

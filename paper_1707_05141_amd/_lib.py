@@ -59,13 +59,18 @@ def lib():
                                ctypes.c_ulonglong, ctypes.c_uint, _ip]
     L.bsvd_sample_omega.argtypes = [_vp, ctypes.c_ulonglong, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                     _vp]
+    L.bsvd_profile_enable.argtypes = [_vp, ctypes.c_int]
+    L.bsvd_profile_read.argtypes = [_vp, ctypes.c_int, _dp, _dp, _dp, _ip]
     _lib = L
     return L
 
 
 def exported_symbols():
     return ["bsvd_create", "bsvd_destroy", "bsvd_last_error", "bsvd_sync", "bsvd_version", "batched_svd",
-            "batched_qr", "batched_rsvd", "bsvd_sample_omega"]
+            "batched_qr", "batched_rsvd", "bsvd_sample_omega", "bsvd_profile_enable", "bsvd_profile_read"]
+
+
+STAGES = ["rng", "sketch", "cgs", "qr", "project", "jacobi", "small", "output"]
 
 
 def i32(a):

@@ -97,9 +97,72 @@ int Ctx::upload_to(size_t dst_off, size_t bytes) {
     return BSVD_OK;
 }
 
+int Ctx::prof_begin(int stage) {
+    if (!prof) return -1;
+    while ((int)evpool.size() < evused + 2) {
+        hipEvent_t ev;
+        if (hipEventCreate(&ev) != hipSuccess) return -1;
+        evpool.push_back(ev);
+    }
+    ProfRec r;
+    r.stage = stage;
+    r.ev0 = evused++;
+    r.ev1 = evused++;
+    r.bytes = 0.0;
+    r.flops = 0.0;
+    hipEventRecord(evpool[r.ev0], stream);
+    recs.push_back(r);
+    return (int)recs.size() - 1;
+}
+
+void Ctx::prof_end(int idx, double bytes, double flops) {
+    if (idx < 0) return;
+    ProfRec &r = recs[idx];
+    hipEventRecord(evpool[r.ev1], stream);
+    r.bytes = bytes;
+    r.flops = flops;
+}
+
 }  // namespace bsvd
 
 extern "C" {
+
+int bsvd_profile_enable(bsvd_ctx *ctx, int on) {
+    if (!ctx) return BSVD_EARG;
+    Ctx *c = reinterpret_cast<Ctx *>(ctx);
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return c->hip_fail(e, "hipStreamSynchronize");
+    c->prof = on != 0;
+    c->recs.clear();
+    c->evused = 0;
+    return BSVD_OK;
+}
+
+int bsvd_profile_read(bsvd_ctx *ctx, int nstage, double *ms, double *bytes, double *flops, int *launches) {
+    if (!ctx || nstage < 0) return BSVD_EARG;
+    Ctx *c = reinterpret_cast<Ctx *>(ctx);
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return c->hip_fail(e, "hipStreamSynchronize");
+    for (int s = 0; s < nstage; ++s) {
+        if (ms) ms[s] = 0.0;
+        if (bytes) bytes[s] = 0.0;
+        if (flops) flops[s] = 0.0;
+        if (launches) launches[s] = 0;
+    }
+    for (const Ctx::ProfRec &r : c->recs) {
+        if (r.stage < 0 || r.stage >= nstage) continue;
+        float t = 0.0f;
+        e = hipEventElapsedTime(&t, c->evpool[r.ev0], c->evpool[r.ev1]);
+        if (e != hipSuccess) return c->hip_fail(e, "hipEventElapsedTime");
+        if (ms) ms[r.stage] += t;
+        if (bytes) bytes[r.stage] += r.bytes;
+        if (flops) flops[r.stage] += r.flops;
+        if (launches) launches[r.stage] += 1;
+    }
+    c->recs.clear();
+    c->evused = 0;
+    return BSVD_OK;
+}
 
 const char *bsvd_version(void) { return "bsvd 0.1 (gfx950)"; }
 
@@ -128,6 +191,7 @@ void bsvd_destroy(bsvd_ctx *ctx) {
     if (c->dws) hipFree(c->dws);
     if (c->hws) hipHostFree(c->hws);
     if (c->rb) hipHostFree(c->rb);
+    for (hipEvent_t ev : c->evpool) hipEventDestroy(ev);
     hipEventDestroy(c->staged);
     delete c;
 }
@@ -334,11 +398,25 @@ int batched_svd(bsvd_ctx *ctx, int dtype, int batch, const int *m, const int *n,
     const int *djl = reinterpret_cast<const int *>(db + o_jl);
     const int *dql = reinterpret_cast<const int *>(db + o_ql);
     const int *dgl = reinterpret_cast<const int *>(db + o_gl);
+    double qr_fl = 0.0, qr_by = 0.0, j_by = 0.0, g_fl = 0.0, g_by = 0.0;
+    for (int b = 0; b < batch; ++b) {
+        const double M = m[b] >= n[b] ? m[b] : n[b], N = m[b] >= n[b] ? n[b] : m[b];
+        j_by += esz * (use_qr[b] ? N * N : M * N) + esz * (M * N + N * N + N);
+        if (use_qr[b]) {
+            qr_fl += 2.0 * (2.0 * M * N * N - 2.0 * N * N * N / 3.0);
+            qr_by += esz * (2.0 * M * N + N * N);
+            g_fl += 2.0 * M * N * N;
+            g_by += esz * (2.0 * M * N + N * N);
+        }
+    }
+    int pidx = c->prof_begin(BSVD_STAGE_QR);
     for (auto &L : qlaunch) {
         e = launch_qr(dtype, L.first.nb, L.first.seg, L.first.kr, dqd, dql + L.second.first, L.second.second,
                       c->stream);
         if (e != hipSuccess) return c->hip_fail(e, "qr launch");
     }
+    c->prof_end(pidx, qr_by, qr_fl);
+    pidx = c->prof_begin(BSVD_STAGE_JACOBI);
     for (auto &L : jlaunch) {
         if (L.first.kind == JK_WAVE)
             e = launch_jacobi_wave(dtype, L.first.a, L.first.b, dsd, djl + L.second.first, L.second.second, tol,
@@ -348,9 +426,12 @@ int batched_svd(bsvd_ctx *ctx, int dtype, int batch, const int *m, const int *n,
                                   max_sweeps, sweeps, info, c->stream);
         if (e != hipSuccess) return c->hip_fail(e, "jacobi launch");
     }
+    c->prof_end(pidx, j_by, 0.0);
     if (!glist.empty()) {
+        pidx = c->prof_begin(BSVD_STAGE_OUTPUT);
         e = launch_gemm_small(dtype, dgd, dgl, (int)glist.size(), c->stream);
         if (e != hipSuccess) return c->hip_fail(e, "gemm launch");
+        c->prof_end(pidx, g_by, g_fl);
     }
     return BSVD_OK;
 }

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <string>
+#include <vector>
 
 namespace bsvd {
 
@@ -32,6 +33,21 @@ struct Ctx {
     void *rb = nullptr;
     size_t rb_size = 0;
     int ensure_readback(size_t bytes);
+
+    // Per-stage profiling: HIP events recorded on `stream` around launch groups (off by default).
+    struct ProfRec {
+        int stage;
+        int ev0, ev1;
+        double bytes, flops;
+    };
+    bool prof = false;
+    std::vector<hipEvent_t> evpool;
+    int evused = 0;
+    std::vector<ProfRec> recs;
+    // Start a record for `stage`; returns its index or -1 when profiling is off.
+    int prof_begin(int stage);
+    // Close record `idx` with the algorithmic bytes / flops of the launches it brackets.
+    void prof_end(int idx, double bytes, double flops);
 };
 
 }  // namespace bsvd

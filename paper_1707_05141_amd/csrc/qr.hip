@@ -2,11 +2,12 @@
 //
 // One workgroup factors one matrix (m <= SEG * KR rows, n <= NB columns). Thread (c, seg) owns
 // column c and the rows seg, seg + SEG, seg + 2 SEG, ... of it in registers, so a column is spread
-// over SEG consecutive lanes and every column operation (norm, v^T x, rank-1 update) is a
+// over SEG consecutive lanes and every column operation (norm, v^T x, rank-1 update) is a short
 // lane-local serial sum followed by a log2(SEG)-step shuffle reduction; no reduction over the
-// whole workgroup is needed. For each column j the owning lanes publish the column in LDS, every
-// thread derives the reflector from its norm, and the lanes of the trailing columns apply
-// I - 2 v v^T to their own registers. The reflectors overwrite the factored columns in place
+// whole workgroup is needed. Every thread derives reflector j from the published pivot column and
+// its norm, and the lanes of the trailing columns apply I - 2 v v^T to their own registers; the
+// lanes of column j + 1 then publish their freshly updated column and its norm into the other half
+// of a double-buffered LDS slot, so each column costs a single barrier. The reflectors overwrite the factored columns in place
 // (compact [R; V] storage), R is written out, and the thin Q = H_0 H_1 ... H_{k-1} [I; 0] is then
 // formed in place by applying the reflectors in reverse order.
 //
@@ -26,10 +27,12 @@ __device__ __forceinline__ T seg_sum(T v) {
 
 template <typename T, int NB, int SEG, int KR>
 __global__ __launch_bounds__(NB *SEG) void qr_kernel(const QrDesc *__restrict__ descs, const int *__restrict__ list) {
-    __shared__ T vbuf[SEG * KR];
+    // vb[buf] holds the published pivot column, s2b[buf] its squared norm below the diagonal;
+    // the two buffers alternate so that the next pivot can be published during the current step.
+    __shared__ T vb[2][SEG * KR];
+    __shared__ T s2b[2];
     __shared__ T diag[NB];
     __shared__ int skipf[NB];
-    __shared__ T s2sh;
 
     const int inst = list[blockIdx.x];
     const QrDesc D = descs[inst];
@@ -48,24 +51,28 @@ __global__ __launch_bounds__(NB *SEG) void qr_kernel(const QrDesc *__restrict__ 
         x[kk] = (colok && row < m) ? (D.trans ? A[c + (size_t)row * D.lda] : A[row + (size_t)c * D.lda]) : T(0);
     }
 
-    // ---- factorisation -------------------------------------------------------------------
-    for (int j = 0; j < k; ++j) {
-        if (c == j) {
-            T part = T(0);
+    // publish column `col` (this thread's rows) into buffer `buf` with the norm of rows > col
+    auto publish = [&](int col, int buf) {
+        T part = T(0);
 #pragma unroll
-            for (int kk = 0; kk < KR; ++kk) {
-                const int row = seg + SEG * kk;
-                if (row < m) {
-                    vbuf[row] = x[kk];
-                    if (row > j) part += x[kk] * x[kk];
-                }
+        for (int kk = 0; kk < KR; ++kk) {
+            const int row = seg + SEG * kk;
+            if (row < m) {
+                vb[buf][row] = x[kk];
+                if (row > col) part += x[kk] * x[kk];
             }
-            part = seg_sum<T, SEG>(part);
-            if (seg == 0) s2sh = part;
         }
-        __syncthreads();
-        const T s2 = s2sh;
-        const T alpha = vbuf[j];
+        part = seg_sum<T, SEG>(part);
+        if (seg == 0) s2b[buf] = part;
+    };
+
+    // ---- factorisation: one barrier per column ----------------------------------------------
+    if (c == 0 && k > 0) publish(0, 0);
+    __syncthreads();
+    for (int j = 0; j < k; ++j) {
+        const int cur = j & 1;
+        const T s2 = s2b[cur];
+        const T alpha = vb[cur][j];
         const bool skip = (m - j < 2) || (s2 == T(0));
         T beta = alpha, vj = T(0), inv = T(0);
         if (!skip) {
@@ -75,20 +82,32 @@ __global__ __launch_bounds__(NB *SEG) void qr_kernel(const QrDesc *__restrict__ 
             inv = T(1) / sqrt(vj * vj + s2);
         }
         if (!skip && colok && c > j) {
+            // the reflector's rows are kept in registers between the dot product and the update
+            // unless that would push a lane past its register budget (KR >= 32)
+            constexpr bool CACHE_V = KR <= 16;
+            T vv[CACHE_V ? KR : 1];
             T w = T(0);
 #pragma unroll
             for (int kk = 0; kk < KR; ++kk) {
                 const int row = seg + SEG * kk;
-                if (row >= j && row < m) w += ((row == j) ? vj : vbuf[row]) * x[kk];
+                const T v = (row >= j && row < m) ? ((row == j) ? vj : vb[cur][row]) : T(0);
+                if constexpr (CACHE_V) vv[kk] = v;
+                w += v * x[kk];
             }
-            w = seg_sum<T, SEG>(w) * inv;
-            const T w2 = T(2) * w * inv;
+            const T w2 = T(2) * seg_sum<T, SEG>(w) * inv * inv;
 #pragma unroll
             for (int kk = 0; kk < KR; ++kk) {
-                const int row = seg + SEG * kk;
-                if (row >= j && row < m) x[kk] -= w2 * ((row == j) ? vj : vbuf[row]);
+                T v;
+                if constexpr (CACHE_V) {
+                    v = vv[kk];
+                } else {
+                    const int row = seg + SEG * kk;
+                    v = (row >= j && row < m) ? ((row == j) ? vj : vb[cur][row]) : T(0);
+                }
+                x[kk] -= w2 * v;
             }
         }
+        if (c == j + 1 && j + 1 < k) publish(j + 1, cur ^ 1);
         if (c == j) {
 #pragma unroll
             for (int kk = 0; kk < KR; ++kk) {
@@ -114,39 +133,53 @@ __global__ __launch_bounds__(NB *SEG) void qr_kernel(const QrDesc *__restrict__ 
     }
     if (!D.Q) return;
 
-    // ---- thin Q by backward accumulation, in place ---------------------------------------
-    for (int j = k - 1; j >= 0; --j) {
-        if (c == j) {
+    // ---- thin Q = H_0 ... H_{k-1} [I; 0] by backward accumulation, in place ------------------
+    // column j of the compact storage holds v_j in rows >= j; it is published one step ahead.
+    auto publish_v = [&](int col, int buf) {
 #pragma unroll
-            for (int kk = 0; kk < KR; ++kk) {
-                const int row = seg + SEG * kk;
-                if (row >= j && row < m) vbuf[row] = x[kk];
-            }
+        for (int kk = 0; kk < KR; ++kk) {
+            const int row = seg + SEG * kk;
+            if (row >= col && row < m) vb[buf][row] = x[kk];
         }
-        __syncthreads();
+    };
+    if (c == k - 1) publish_v(k - 1, (k - 1) & 1);
+    __syncthreads();
+    for (int j = k - 1; j >= 0; --j) {
+        const int cur = j & 1;
         const bool skip = skipf[j] != 0;
         if (!skip && c > j && c < k) {
+            constexpr bool CACHE_V = KR <= 16;
+            T vv[CACHE_V ? KR : 1];
             T w = T(0);
 #pragma unroll
             for (int kk = 0; kk < KR; ++kk) {
                 const int row = seg + SEG * kk;
-                if (row >= j && row < m) w += vbuf[row] * x[kk];
+                const T v = (row >= j && row < m) ? vb[cur][row] : T(0);
+                if constexpr (CACHE_V) vv[kk] = v;
+                w += v * x[kk];
             }
             w = T(2) * seg_sum<T, SEG>(w);
 #pragma unroll
             for (int kk = 0; kk < KR; ++kk) {
-                const int row = seg + SEG * kk;
-                if (row >= j && row < m) x[kk] -= w * vbuf[row];
+                T v;
+                if constexpr (CACHE_V) {
+                    v = vv[kk];
+                } else {
+                    const int row = seg + SEG * kk;
+                    v = (row >= j && row < m) ? vb[cur][row] : T(0);
+                }
+                x[kk] -= w * v;
             }
         }
+        if (c == j - 1) publish_v(j - 1, cur ^ 1);
         if (c == j) {
-            const T vjj = vbuf[j];
+            const T vjj = vb[cur][j];
 #pragma unroll
             for (int kk = 0; kk < KR; ++kk) {
                 const int row = seg + SEG * kk;
                 if (row < m) {
                     const T e = (row == j) ? T(1) : T(0);
-                    x[kk] = row < j ? T(0) : (skip ? e : e - T(2) * vbuf[row] * vjj);
+                    x[kk] = row < j ? T(0) : (skip ? e : e - T(2) * x[kk] * vjj);
                 }
             }
         }
@@ -162,8 +195,9 @@ __global__ __launch_bounds__(NB *SEG) void qr_kernel(const QrDesc *__restrict__ 
     }
 }
 
-// Shape selection: NB = next power of two >= n (at least 8), SEG the smallest power of two with
-// SEG * 64 >= m and NB * SEG >= 64, KR = next power of two >= ceil(m / SEG) (at least 8).
+// Shape selection: NB = next power of two >= n (at least 8); at most KRMAX(NB) rows per lane
+// (8, 8, 16, 32 for NB = 8, 16, 32, 64) so that registers stay low; SEG = lanes per column, at least
+// 64 / NB so that a wave is full; KR = rows per lane (at least 4).
 static int p2(int x) {
     int p = 1;
     while (p < x) p <<= 1;
@@ -171,14 +205,15 @@ static int p2(int x) {
 }
 
 bool qr_config(int m, int n, int *nb, int *seg, int *kr) {
-    int NB = p2(n < 8 ? 8 : n);
-    if (NB > 64 || m > 512 || m < 1 || n < 1) return false;
-    int SEG = 1;
-    while (SEG * 64 < m || NB * SEG < 64) SEG <<= 1;
-    if (NB * SEG > 512) return false;
+    if (m < 1 || n < 1 || m > 512) return false;
+    const int NB = p2(n < 8 ? 8 : n);
+    if (NB > 64) return false;
+    const int krmax = NB <= 16 ? 8 : (NB == 32 ? 16 : 32);
+    int SEG = p2((m + krmax - 1) / krmax);
+    if (SEG < 64 / NB) SEG = 64 / NB;
+    if (SEG > 64 || NB * SEG > 1024) return false;
     int KR = p2((m + SEG - 1) / SEG);
-    if (KR < 8) KR = 8;
-    if (KR > 64) return false;
+    if (KR < 4) KR = 4;
     *nb = NB;
     *seg = SEG;
     *kr = KR;
@@ -199,28 +234,32 @@ static hipError_t qr_launch_one(const QrDesc *d, const int *list, int count, hip
 hipError_t launch_qr(int dtype, int nb, int seg, int kr, const QrDesc *d, const int *list, int count,
                      hipStream_t st) {
     if (count <= 0) return hipSuccess;
+    BSVD_QR_CASE(8, 8, 4)
     BSVD_QR_CASE(8, 8, 8)
-    BSVD_QR_CASE(8, 8, 16)
-    BSVD_QR_CASE(8, 8, 32)
-    BSVD_QR_CASE(8, 8, 64)
+    BSVD_QR_CASE(8, 16, 8)
+    BSVD_QR_CASE(8, 32, 8)
+    BSVD_QR_CASE(8, 64, 8)
+    BSVD_QR_CASE(16, 4, 4)
     BSVD_QR_CASE(16, 4, 8)
-    BSVD_QR_CASE(16, 4, 16)
-    BSVD_QR_CASE(16, 4, 32)
-    BSVD_QR_CASE(16, 4, 64)
-    BSVD_QR_CASE(16, 8, 64)
+    BSVD_QR_CASE(16, 8, 8)
+    BSVD_QR_CASE(16, 16, 8)
+    BSVD_QR_CASE(16, 32, 8)
+    BSVD_QR_CASE(16, 64, 8)
+    BSVD_QR_CASE(32, 2, 4)
     BSVD_QR_CASE(32, 2, 8)
     BSVD_QR_CASE(32, 2, 16)
-    BSVD_QR_CASE(32, 2, 32)
-    BSVD_QR_CASE(32, 2, 64)
-    BSVD_QR_CASE(32, 4, 64)
-    BSVD_QR_CASE(32, 8, 64)
+    BSVD_QR_CASE(32, 4, 16)
+    BSVD_QR_CASE(32, 8, 16)
+    BSVD_QR_CASE(32, 16, 16)
+    BSVD_QR_CASE(32, 32, 16)
+    BSVD_QR_CASE(64, 1, 4)
     BSVD_QR_CASE(64, 1, 8)
     BSVD_QR_CASE(64, 1, 16)
     BSVD_QR_CASE(64, 1, 32)
-    BSVD_QR_CASE(64, 1, 64)
-    BSVD_QR_CASE(64, 2, 64)
-    BSVD_QR_CASE(64, 4, 64)
-    BSVD_QR_CASE(64, 8, 64)
+    BSVD_QR_CASE(64, 2, 32)
+    BSVD_QR_CASE(64, 4, 32)
+    BSVD_QR_CASE(64, 8, 32)
+    BSVD_QR_CASE(64, 16, 32)
     return hipErrorInvalidValue;
 }
 

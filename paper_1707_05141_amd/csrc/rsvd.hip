@@ -9,8 +9,8 @@
 //                    staged in LDS, every element of X read once. Optional per-tile partial sums of
 //                    X^2 (||A||_F^2) and of the outputs' squares.
 //   gemm_tn_kernel   C = X^T Y with the reduction over the tall dimension (B^T = A^T Q, H = Q^T Y_b):
-//                    one lane per column of X, row chunks of Y staged in LDS. Optional partial sum of
-//                    the outputs' squares (||B||_F^2).
+//                    row chunks of a 64-column tile of X loaded coalesced into LDS, one lane per column
+//                    and output group. Optional partial sum of the outputs' squares (||B||_F^2).
 //   small kernels    per-instance decisions: finishing ||A||_F^2, the growth test, the exact check
 //                    ||A||_F^2 - ||Q^T A||_F^2 <= eps^2 ||A||_F^2, the truncation rule and outputs.
 // Partial sums are written per tile and reduced in a fixed order, so results are bitwise
@@ -150,52 +150,69 @@ __global__ __launch_bounds__(64) void gemm_nn_kernel(const MMDesc *__restrict__ 
 
 // ---------------------------------------------------------------------------------------------
 // C (K x N) = X^T Y, X column-major M x K, Y column-major M x N, C column-major K x N.
-// One 64-lane workgroup per 64 columns of X; N <= NMAX.
+// One 256-thread workgroup per 64 columns of X. Row chunks of the X tile are loaded coalesced
+// (consecutive lanes read consecutive rows of a column) into LDS transposed, together with the
+// matching rows of Y; lane (c, g) then accumulates column c against output group g (NMAX / 4
+// outputs). Every element of X is read from memory once.
 // ---------------------------------------------------------------------------------------------
 template <int NMAX>
-__global__ __launch_bounds__(64) void gemm_tn_kernel(const MMDesc *__restrict__ d, const int2 *__restrict__ tiles) {
+__global__ __launch_bounds__(256) void gemm_tn_kernel(const MMDesc *__restrict__ d, const int2 *__restrict__ tiles) {
     constexpr int RC = 32;
-    __shared__ double ys[RC * NMAX];
+    constexpr int NJ = NMAX / 4;
+    __shared__ double xs[RC][65];
+    __shared__ double ys[RC][NMAX];
+    __shared__ double red[4];
     const int2 tl = tiles[blockIdx.x];
     const MMDesc D = d[tl.x];
-    const int lane = threadIdx.x;
-    const int c = tl.y * 64 + lane;
-    const bool cok = c < D.K;
-    double acc[NMAX];
+    const int t = threadIdx.x;
+    const int c = t & 63;
+    const int g = t >> 6;
+    const int c0 = tl.y * 64;
+    const int col = c0 + c;
+    const bool cok = col < D.K;
+    double acc[NJ];
 #pragma unroll
-    for (int j = 0; j < NMAX; ++j) acc[j] = 0.0;
+    for (int j = 0; j < NJ; ++j) acc[j] = 0.0;
     for (int r0 = 0; r0 < D.M; r0 += RC) {
         const int rc = (D.M - r0) < RC ? (D.M - r0) : RC;
-        for (int idx = lane; idx < RC * NMAX; idx += 64) {
+#pragma unroll
+        for (int i = 0; i < (RC * 64) / 256; ++i) {
+            const int idx = t + 256 * i;
+            const int cc = idx / RC, rr = idx - (idx / RC) * RC;
+            double v = 0.0;
+            if (rr < rc && c0 + cc < D.K) v = D.X[(r0 + rr) + (size_t)(c0 + cc) * D.ldx];
+            xs[rr][cc] = v;
+        }
+        for (int idx = t; idx < RC * NMAX; idx += 256) {
             const int j = idx / RC, rr = idx - (idx / RC) * RC;
-            double y = 0.0;
-            if (j < D.N && rr < rc) y = D.Y[(r0 + rr) + (size_t)j * D.ldy];
-            ys[rr * NMAX + j] = y;
+            double v = 0.0;
+            if (j < D.N && rr < rc) v = D.Y[(r0 + rr) + (size_t)j * D.ldy];
+            ys[rr][j] = v;
         }
         __syncthreads();
-        if (cok) {
-            const double *xp = D.X + r0 + (size_t)c * D.ldx;
-            for (int rr = 0; rr < rc; ++rr) {
-                const double x = xp[rr];
+        for (int rr = 0; rr < rc; ++rr) {
+            const double x = xs[rr][c];
 #pragma unroll
-                for (int j = 0; j < NMAX; ++j) acc[j] = fma(x, ys[rr * NMAX + j], acc[j]);
-            }
+            for (int j = 0; j < NJ; ++j) acc[j] = fma(x, ys[rr][g * NJ + j], acc[j]);
         }
         __syncthreads();
     }
     double cs = 0.0;
     if (cok) {
 #pragma unroll
-        for (int j = 0; j < NMAX; ++j) {
-            if (j < D.N) {
-                D.C[c + (size_t)j * D.ldc] = acc[j];
+        for (int j = 0; j < NJ; ++j) {
+            const int jj = g * NJ + j;
+            if (jj < D.N) {
+                D.C[col + (size_t)jj * D.ldc] = acc[j];
                 cs = fma(acc[j], acc[j], cs);
             }
         }
     }
     if (D.csq) {
         cs = wave_sum(cs);
-        if (lane == 0) D.csq[tl.y] = cs;
+        if (c == 0) red[g] = cs;
+        __syncthreads();
+        if (t == 0) D.csq[tl.y] = (red[0] + red[1]) + (red[2] + red[3]);
     }
 }
 
@@ -329,10 +346,10 @@ hipError_t launch_gemm_nn(int nmax, const MMDesc *d, const int2 *tiles, int ntil
 hipError_t launch_gemm_tn(int nmax, const MMDesc *d, const int2 *tiles, int ntiles, hipStream_t st) {
     if (ntiles <= 0) return hipSuccess;
     switch (nmax) {
-        case 8: hipLaunchKernelGGL(gemm_tn_kernel<8>, dim3(ntiles), dim3(64), 0, st, d, tiles); break;
-        case 16: hipLaunchKernelGGL(gemm_tn_kernel<16>, dim3(ntiles), dim3(64), 0, st, d, tiles); break;
-        case 32: hipLaunchKernelGGL(gemm_tn_kernel<32>, dim3(ntiles), dim3(64), 0, st, d, tiles); break;
-        case 64: hipLaunchKernelGGL(gemm_tn_kernel<64>, dim3(ntiles), dim3(64), 0, st, d, tiles); break;
+        case 8: hipLaunchKernelGGL(gemm_tn_kernel<8>, dim3(ntiles), dim3(256), 0, st, d, tiles); break;
+        case 16: hipLaunchKernelGGL(gemm_tn_kernel<16>, dim3(ntiles), dim3(256), 0, st, d, tiles); break;
+        case 32: hipLaunchKernelGGL(gemm_tn_kernel<32>, dim3(ntiles), dim3(256), 0, st, d, tiles); break;
+        case 64: hipLaunchKernelGGL(gemm_tn_kernel<64>, dim3(ntiles), dim3(256), 0, st, d, tiles); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -311,6 +311,15 @@ extern "C" int batched_rsvd(bsvd_ctx *ctx, int batch, const int *m, const int *n
                 hgi[i] = GrowItem{b, q.ell0, 1, 0};
                 q.ell = q.ell0;
             }
+            double skb = 0, skf = 0, rgb = 0, qrf = 0, qrb = 0;
+            for (int b : init) {
+                const Inst &q = I[b];
+                skb += 8.0 * ((double)q.m * q.n + (double)q.m * q.ell0 + (double)q.n * q.ell0);
+                skf += 2.0 * q.m * q.n * (double)q.ell0;
+                rgb += 8.0 * q.n * (double)q.ell0;
+                qrf += 4.0 * q.m * (double)q.ell0 * q.ell0;
+                qrb += 16.0 * q.m * (double)q.ell0;
+            }
             int2 *drt;
             int2 *hrt = p.put<int2>(rt.size(), &drt);
             if (hrt) std::copy(rt.begin(), rt.end(), hrt);
@@ -320,12 +329,20 @@ extern "C" int batched_rsvd(bsvd_ctx *ctx, int batch, const int *m, const int *n
             std::vector<std::pair<QKey, std::pair<const int *, int>>> ql;
             if ((rc = pack_qr(p, qv, ql, &dq))) return c->fail(rc, "internal: no QR kernel for the initial block");
             if ((rc = commit(p))) return rc;
+            int pi = c->prof_begin(BSVD_STAGE_RNG);
             e = launch_rng(drd, drt, (int)rt.size(), seed, c->stream);
             if (e != hipSuccess) return c->hip_fail(e, "rng launch");
+            c->prof_end(pi, rgb, 0.0);
+            pi = c->prof_begin(BSVD_STAGE_SKETCH);
             if ((rc = launch_mm(mm))) return rc;
+            c->prof_end(pi, skb, skf);
+            pi = c->prof_begin(BSVD_STAGE_QR);
             if ((rc = launch_qrs(dq, ql))) return rc;
+            c->prof_end(pi, qrb, qrf);
+            pi = c->prof_begin(BSVD_STAGE_SMALL);
             e = launch_init_norm(dstate, dgi, (int)init.size(), c->stream);
             if (e != hipSuccess) return c->hip_fail(e, "init launch");
+            c->prof_end(pi, 0.0, 0.0);
             pend_check = init;
         }
     }
@@ -344,11 +361,21 @@ extern "C" int batched_rsvd(bsvd_ctx *ctx, int batch, const int *m, const int *n
             std::vector<int2> rt;
             std::map<int, MMGroup> sk, tn1, nn1, tn2, nn2;
             std::vector<QrDesc> qv;
+            double skb = 0, skf = 0, rgb = 0, qrf = 0, qrb = 0, cgb = 0, cgf = 0;
             for (int i = 0; i < G; ++i) {
                 const int b = grow[i];
                 Inst &q = I[b];
                 const int blk = std::min(GROW_BLK, q.cap - q.ell);
                 const int first = q.ell == 0;
+                skb += 8.0 * ((double)q.m * q.n + (double)q.m * blk + (double)q.n * blk);
+                skf += 2.0 * q.m * q.n * (double)blk;
+                rgb += 8.0 * q.n * (double)blk;
+                qrf += 4.0 * q.m * (double)blk * blk;
+                qrb += 16.0 * q.m * (double)blk;
+                if (!first) {
+                    cgb += 2.0 * 8.0 * (2.0 * q.m * q.ell + 3.0 * q.m * blk + 2.0 * q.ell * blk);
+                    cgf += 4.0 * 2.0 * q.m * (double)q.ell * blk;
+                }
                 hrd[i] = RngDesc{dptr(q.oOm), q.n, blk, q.ell, blk, b};
                 for (int t = 0; t < cdiv(q.n * blk, 256); ++t) rt.push_back(make_int2(i, t));
                 MMGroup &g = sk[8];
@@ -389,14 +416,24 @@ extern "C" int batched_rsvd(bsvd_ctx *ctx, int batch, const int *m, const int *n
             std::vector<std::pair<QKey, std::pair<const int *, int>>> ql;
             if ((rc = pack_qr(p, qv, ql, &dq))) return c->fail(rc, "internal: no QR kernel for a sample block");
             if ((rc = commit(p))) return rc;
+            int pi = c->prof_begin(BSVD_STAGE_RNG);
             e = launch_rng(drd, drt, (int)rt.size(), seed, c->stream);
             if (e != hipSuccess) return c->hip_fail(e, "rng launch");
-            if ((rc = launch_mm(msk)) || (rc = launch_mm(mt1)) || (rc = launch_mm(mn1)) || (rc = launch_mm(mt2)) ||
-                (rc = launch_mm(mn2)))
+            c->prof_end(pi, rgb, 0.0);
+            pi = c->prof_begin(BSVD_STAGE_SKETCH);
+            if ((rc = launch_mm(msk))) return rc;
+            c->prof_end(pi, skb, skf);
+            pi = c->prof_begin(BSVD_STAGE_CGS);
+            if ((rc = launch_mm(mt1)) || (rc = launch_mm(mn1)) || (rc = launch_mm(mt2)) || (rc = launch_mm(mn2)))
                 return rc;
+            c->prof_end(pi, cgb, cgf);
+            pi = c->prof_begin(BSVD_STAGE_QR);
             if ((rc = launch_qrs(dq, ql))) return rc;
+            c->prof_end(pi, qrb, qrf);
+            pi = c->prof_begin(BSVD_STAGE_SMALL);
             e = launch_grow_decide(dstate, dgi, G, dflags, c->stream);
             if (e != hipSuccess) return c->hip_fail(e, "decide launch");
+            c->prof_end(pi, 0.0, 0.0);
             if ((rc = readback(G))) return rc;
             std::vector<int> still;
             for (int i = 0; i < G; ++i) (rb[i] ? pend_check : still).push_back(grow[i]);
@@ -407,9 +444,12 @@ extern "C" int batched_rsvd(bsvd_ctx *ctx, int batch, const int *m, const int *n
             if ((rc = new_packer(p))) return rc;
             const int P = (int)pend_check.size();
             std::map<int, MMGroup> bt;
+            double pjb = 0, pjf = 0;
             for (int i = 0; i < P; ++i) {
                 const int b = pend_check[i];
                 const Inst &q = I[b];
+                pjb += 8.0 * ((double)q.m * q.n + (double)q.m * q.ell + (double)q.n * q.ell);
+                pjf += 2.0 * q.m * q.n * (double)q.ell;
                 MMGroup &g = bt[nmax_for(q.ell)];
                 g.desc.push_back(mm_nn(static_cast<const double *>(A[b]), q.lda, dptr(q.oQ), q.m, 0, dptr(q.oBt), q.n,
                                        q.m, q.ell, q.n, 1.0, 0.0, nullptr, dptr(q.oBsq)));
@@ -422,9 +462,13 @@ extern "C" int batched_rsvd(bsvd_ctx *ctx, int batch, const int *m, const int *n
             std::vector<Pending> mb;
             pack_mm(p, bt, 1, mb);
             if ((rc = commit(p))) return rc;
+            int pi = c->prof_begin(BSVD_STAGE_PROJECT);
             if ((rc = launch_mm(mb))) return rc;
+            c->prof_end(pi, pjb, pjf);
+            pi = c->prof_begin(BSVD_STAGE_SMALL);
             e = launch_check(dstate, dl, P, dflags, c->stream);
             if (e != hipSuccess) return c->hip_fail(e, "check launch");
+            c->prof_end(pi, 0.0, 0.0);
             if ((rc = readback(P))) return rc;
             for (int i = 0; i < P; ++i) {
                 const int b = pend_check[i];
@@ -480,7 +524,17 @@ extern "C" int batched_rsvd(bsvd_ctx *ctx, int batch, const int *m, const int *n
         std::vector<std::pair<QKey, std::pair<const int *, int>>> ql;
         if ((rc = pack_qr(p, qv, ql, &dq))) return c->fail(rc, "internal: no QR kernel for B^T");
         if ((rc = commit(p))) return rc;
+        double qrf = 0, qrb = 0, jb_ = 0;
+        for (int b : finished) {
+            const Inst &q = I[b];
+            qrf += 2.0 * (2.0 * q.n * (double)q.ell * q.ell - 2.0 * (double)q.ell * q.ell * q.ell / 3.0);
+            qrb += 8.0 * (2.0 * q.n * (double)q.ell + (double)q.ell * q.ell);
+            jb_ += 8.0 * 4.0 * (double)q.ell * q.ell;
+        }
+        int pi = c->prof_begin(BSVD_STAGE_QR);
         if ((rc = launch_qrs(dq, ql))) return rc;
+        c->prof_end(pi, qrb, qrf);
+        pi = c->prof_begin(BSVD_STAGE_JACOBI);
         for (auto &L : jl) {
             // info per descriptor position -> djinfo[position]
             if (L.first.kind == JK_WAVE)
@@ -491,8 +545,11 @@ extern "C" int batched_rsvd(bsvd_ctx *ctx, int batch, const int *m, const int *n
                                       djinfo, c->stream);
             if (e != hipSuccess) return c->hip_fail(e, "jacobi launch");
         }
+        c->prof_end(pi, jb_, 0.0);
+        pi = c->prof_begin(BSVD_STAGE_SMALL);
         e = launch_finalize(dstate, dl, F, rank, err_est, info, djinfo, drankc, c->stream);
         if (e != hipSuccess) return c->hip_fail(e, "finalize launch");
+        c->prof_end(pi, 0.0, 0.0);
         e = hipMemcpyAsync(c->rb, drankc, sizeof(int) * (size_t)F, hipMemcpyDeviceToHost, c->stream);
         if (e != hipSuccess) return c->hip_fail(e, "hipMemcpyAsync(rank)");
         e = hipStreamSynchronize(c->stream);
@@ -505,11 +562,14 @@ extern "C" int batched_rsvd(bsvd_ctx *ctx, int batch, const int *m, const int *n
         Packer p;
         if ((rc = new_packer(p))) return rc;
         std::map<int, MMGroup> out;
+        double ob = 0, of = 0;
         for (int i = 0; i < F; ++i) {
             const int b = finished[i];
             const Inst &q = I[b];
             const int k = kk[i];
             if (k <= 0) continue;
+            ob += 8.0 * ((double)(q.m + q.n) * q.ell + (double)(q.m + q.n) * k + 2.0 * q.ell * k);
+            of += 2.0 * (double)(q.m + q.n) * q.ell * k;
             MMGroup &g = out[nmax_for(k)];
             if (U && U[b]) {
                 g.desc.push_back(mm_nn(dptr(q.oQ), q.m, dptr(q.oUR), q.cap, 0, static_cast<double *>(U[b]), ldu[b], q.m,
@@ -525,7 +585,9 @@ extern "C" int batched_rsvd(bsvd_ctx *ctx, int batch, const int *m, const int *n
         std::vector<Pending> mo;
         pack_mm(p, out, 0, mo);
         if ((rc = commit(p))) return rc;
+        int pi = c->prof_begin(BSVD_STAGE_OUTPUT);
         if ((rc = launch_mm(mo))) return rc;
+        c->prof_end(pi, ob, of);
     }
     return BSVD_OK;
 }

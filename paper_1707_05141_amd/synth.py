@@ -120,3 +120,38 @@ def batch_prescribed(batch: int, m: int, n: int, sigma: np.ndarray, seed: int, c
         V = batch_haar(rng, c, n, k)
         out[s0:s0 + c] = np.matmul(U * sigma[None, None, :], np.transpose(V, (0, 2, 1)))
     return out
+
+
+def kernel_blocks_packed(m, n, seed, kind="exp", corr=0.1, device="cuda", first_inst=0):
+    """Kernel blocks for instances first_inst .. first_inst+len(m)-1, evaluated on `device` with
+    torch and packed column-major, 256-byte aligned (same layout as pack_colmajor). The points of
+    each instance come from the same per-instance host stream as kernel_block(), so a block equals
+    kernel_block(m_i, n_i, seed, first_inst + i, kind) up to rounding of the distance evaluation.
+    Returns (buffer, element offsets)."""
+    import torch
+    m = np.asarray(m, dtype=np.int64)
+    n = np.asarray(n, dtype=np.int64)
+    sizes = m * n
+    padded = (sizes + 31) // 32 * 32
+    offs = np.concatenate([[0], np.cumsum(padded)[:-1]]).astype(np.int64) if len(m) else np.zeros(0, np.int64)
+    buf = torch.zeros(int(padded.sum()) if len(m) else 1, dtype=torch.float64, device=device)
+    kinds = kind if isinstance(kind, (list, tuple, np.ndarray)) else [kind] * len(m)
+    groups = {}
+    for i in range(len(m)):
+        groups.setdefault((int(m[i]), int(n[i]), kinds[i]), []).append(i)
+    for (mm, nn, kd), idx in groups.items():
+        for s0 in range(0, len(idx), 512):
+            part = idx[s0:s0 + 512]
+            X = np.empty((len(part), mm, 2))
+            Y = np.empty((len(part), nn, 2))
+            for j, i in enumerate(part):
+                X[j], Y[j] = kernel_points(mm, nn, seed, first_inst + i)
+            Xt = torch.from_numpy(X).to(device)
+            Yt = torch.from_numpy(Y).to(device)
+            d = torch.sqrt(((Yt[:, :, None, :] - Xt[:, None, :, :]) ** 2).sum(-1))  # [B, n, m]: column-major
+            blk = torch.exp(-d / corr) if kd == "exp" else 1.0 / d
+            flat = blk.reshape(len(part), -1)
+            for j, i in enumerate(part):
+                o = int(offs[i])
+                buf[o:o + mm * nn] = flat[j]
+    return buf, offs
