@@ -292,7 +292,62 @@ def cpu_baseline_rsvd(m, n, dseed, oseed, eps, max_rank, synth, oracle):
                        % (len(picks), dt))
 
 
-WORKLOADS = {"c1": run_c1, "c2": run_c2, "c4": run_c4}
+def run_c3(args, torch, P, synth):
+    """500 matrices 512 x 256, A = U diag(sigma) V^T with Haar U, V and sigma_i geometric from 1 to
+    1e-10: one-sided block Jacobi in HBM (Gram path, MFMA Gram and block rotations), FP64 and FP32."""
+    from paper_1707_05141_amd import _lib
+    b, m, n = 500, 512, 256
+    sig = synth.graded_sigma_log(n, 10.0)
+    A_np = synth.batch_prescribed(b, m, n, sig, seed=3)
+    flags = _lib.SVD_FORCE_BLOCK | {8: _lib.SVD_BLOCK_W8, 16: 0, 32: _lib.SVD_BLOCK_W32}[args.block_w]
+    out = {}
+    for dt, name in ((torch.float64, "f64"), (torch.float32, "f32")):
+        A = torch.from_numpy(A_np).to(device="cuda", dtype=dt)
+        Acm = P.colmajor(A)
+        S = torch.empty((b, n), dtype=dt, device="cuda")
+        U = torch.empty((b, n, m), dtype=dt, device="cuda")
+        V = torch.empty((b, n, n), dtype=dt, device="cuda")
+        sw = torch.empty(b, dtype=torch.int32, device="cuda")
+        info = torch.empty(b, dtype=torch.int32, device="cuda")
+        ptr = lambda t: t.data_ptr() + t.stride(0) * t.element_size() * np.arange(b, dtype=np.uint64)
+        code = 0 if dt == torch.float64 else 1
+        call = lambda: P.batched_svd(np.full(b, m), np.full(b, n), ptr(Acm), np.full(b, m), ptr(S), ptr(U),
+                                     np.full(b, m), ptr(V), np.full(b, n), dtype=code, sweeps=sw, info=info,
+                                     flags=flags)
+        for _ in range(args.warmup):
+            call()
+        torch.cuda.synchronize()
+        P.profile_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            call()
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / args.steps
+        prof = P.profile_read()
+        P.profile_enable(False)
+        err = float(np.max(np.abs(S.double().cpu().numpy() - sig[None, :])))
+        out[name] = dict(ms=wall * 1e3, info_max=int(info.max().item()), mean_block_sweeps=float(sw.float().mean().item()),
+                         max_sigma_err=err, prof=prof)
+    f64 = out["f64"]
+    assert f64["info_max"] == 0 and f64["max_sigma_err"] <= 1e-12, f64
+    gp = f64["prof"]
+    gram = gp["sketch"]
+    achieved = gram["flops"] / (gram["ms"] * 1e-3) / 1e12
+    point_flops = 9.0e9 * b  # point-Jacobi reference: 36 sweeps x 32,640 pairs x 7,680 flops per matrix
+    res = dict(value=b / (f64["ms"] * 1e-3), unit="SVDs/s", ms_per_step=f64["ms"], dtype="f64",
+               config=dict(workload="block_jacobi_500x512x256_kappa1e10", batch=b, block_w=args.block_w,
+                           f64=dict(ms=f64["ms"], sweeps=f64["mean_block_sweeps"], max_sigma_err=f64["max_sigma_err"]),
+                           f32=dict(ms=out["f32"]["ms"], sweeps=out["f32"]["mean_block_sweeps"],
+                                    max_sigma_err=out["f32"]["max_sigma_err"], info_max=out["f32"]["info_max"]),
+                           stage_ms_per_step={k: v["ms"] / args.steps for k, v in gp.items()},
+                           point_jacobi_equiv_tflop_per_s=point_flops / (f64["ms"] * 1e-3) / 1e12),
+               roofline=dict(bound="mfma", achieved=achieved, peak=FP64_PEAK_TFLOPS, unit="TFLOP/s",
+                             frac=achieved / FP64_PEAK_TFLOPS, traffic=None, kernel="bj_gram_kernel (FP64 MFMA)",
+                             kernel_ms=gram["ms"] / max(1, gram["launches"])))
+    return res
+
+
+WORKLOADS = {"c1": run_c1, "c2": run_c2, "c3": run_c3, "c4": run_c4}
 
 
 def main():
@@ -302,6 +357,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c1", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
+    ap.add_argument("--block-w", type=int, default=16, choices=(8, 16, 32))
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on exactly one GPU; --gpus %d is not supported "

@@ -49,7 +49,9 @@ enum {
     BSVD_SVD_FORCE_BLOCK = 1u << 2, /* block Jacobi in HBM, Gram path (Section 6.1) */
     BSVD_SVD_QR_FIRST = 1u << 3,    /* Householder QR first, then Jacobi of R (also for square inputs) */
     BSVD_SVD_NO_QR = 1u << 4,       /* never run the QR pre-step (default: QR first when m != n) */
-    BSVD_SVD_JACOBI_ON_R = 1u << 5  /* after QR, rotate the columns of R instead of its rows */
+    BSVD_SVD_JACOBI_ON_R = 1u << 5, /* after QR, rotate the columns of R instead of its rows */
+    BSVD_SVD_BLOCK_W8 = 1u << 6,    /* block Jacobi with 8-column blocks (default 16) */
+    BSVD_SVD_BLOCK_W32 = 1u << 7    /* block Jacobi with 32-column blocks */
 };
 
 /* Flags for batched_rsvd. */
@@ -106,7 +108,11 @@ const char *bsvd_version(void);
  * reduced by Householder QR (Section 2.1), W = Q R; the SVD of the min(m,n) x min(m,n) triangle R is
  * then computed by one-sided Jacobi applied to the columns of R^T (the rows of R), which converges
  * in far fewer sweeps than on R itself (the QR preprocessing that Section 6.3 names as a remedy for
- * slow block-Jacobi convergence), and U = Q U_R.
+ * slow block-Jacobi convergence), and U = Q U_R. Matrices too large for the register and LDS kernels
+ * (or all of them with BSVD_SVD_FORCE_BLOCK) use the one-sided block Jacobi of Section 6.1
+ * (Algorithm 3, Gram path): pairs of w-column blocks are orthogonalised by the SVD of their
+ * 2w x 2w Gram matrix, visited in round-robin order, until every pair's scaled off-diagonal
+ * max |G_ab| / sqrt(G_aa G_bb) is <= tol; sweeps then counts block sweeps.
  *
  *   dtype       BSVD_F64 (or BSVD_F32: data and rotations in FP32, angles and norms in FP64)
  *   batch       number of instances (0 is allowed and does nothing)

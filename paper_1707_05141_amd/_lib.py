@@ -22,6 +22,8 @@ SVD_FORCE_BLOCK = 1 << 2
 SVD_QR_FIRST = 1 << 3
 SVD_NO_QR = 1 << 4
 SVD_JACOBI_ON_R = 1 << 5
+SVD_BLOCK_W8 = 1 << 6
+SVD_BLOCK_W32 = 1 << 7
 
 RSVD_FIXED = 1 << 0
 

@@ -1,0 +1,233 @@
+// Host driver of the one-sided block Jacobi, Gram path (Section 6.1, Algorithm 3).
+//
+// Block pairs are visited in round-robin order: in step s of a sweep, each matrix with nb blocks
+// processes nb/2 disjoint pairs (block nb-1 meets block s, block p meets (2s - p) mod (nb-1)), so a
+// step is one Gram launch, one batched Jacobi SVD of all Gram matrices and one apply launch over all
+// (matrix, pair) tasks of the unfinished matrices. After each sweep the per-matrix maximum of the
+// pair measures is read back (one synchronisation) and converged matrices drop out.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <vector>
+
+#include "../../include/bsvd.h"
+#include "block_jacobi.hpp"
+#include "common.hpp"
+#include "ctx.hpp"
+#include "plan.hpp"
+
+namespace bsvd {
+
+int block_jacobi_run(Ctx *c, int dtype, int w, const std::vector<int> &insts, const int *m, const int *n,
+                     const void *const *A, const int *lda, void *const *S, void *const *U, const int *ldu,
+                     void *const *V, const int *ldv, double tol, int max_sweeps, int *sweeps, int *info) {
+    const int nm = (int)insts.size();
+    if (nm == 0) return BSVD_OK;
+    const size_t esz = dtype == BSVD_F64 ? 8 : 4;
+    const int K = 2 * w;
+    struct HM {
+        int M, N, NP, nb;
+        size_t oW, oV, oG, oVG, oSg, oPS;
+    };
+    std::vector<HM> hm(nm);
+    size_t dsz = 1 << 16;
+    int nbmax = 0, nmax = 0;
+    for (int i = 0; i < nm; ++i) {
+        const int b = insts[i];
+        HM &h = hm[i];
+        h.M = std::max(m[b], n[b]);
+        h.N = std::min(m[b], n[b]);
+        h.NP = (h.N + K - 1) / K * K;
+        h.nb = h.NP / w;
+        nbmax = std::max(nbmax, h.nb);
+        nmax = std::max(nmax, h.N);
+        dsz += 256 + (size_t)(h.nb / 2) * (sizeof(BjTask) + sizeof(SvdDesc) + 2 * sizeof(int)) + 512;
+    }
+    dsz = (dsz + 4095) & ~(size_t)4095;
+    Arena ar;
+    ar.off = dsz;
+    const size_t oMats = ar.alloc(sizeof(BjMat) * (size_t)nm);
+    const size_t oFlags = ar.alloc(sizeof(int) * (size_t)nm);
+    for (int i = 0; i < nm; ++i) {
+        HM &h = hm[i];
+        const int npairs = h.nb * (h.nb - 1) / 2;
+        h.oW = ar.alloc(esz * (size_t)h.M * h.NP);
+        h.oV = ar.alloc(esz * (size_t)h.NP * h.NP);
+        h.oG = ar.alloc(8 * (size_t)(h.nb / 2) * K * K);
+        h.oVG = ar.alloc(8 * (size_t)(h.nb / 2) * K * K);
+        h.oSg = ar.alloc(8 * (size_t)(h.nb / 2) * K);
+        h.oPS = ar.alloc(16 * (size_t)npairs);
+    }
+    int rc = c->ensure_device(ar.off);
+    if (rc) return rc;
+    rc = c->ensure_host(std::max(dsz, sizeof(BjMat) * (size_t)nm));
+    if (rc) return rc;
+    rc = c->ensure_readback(sizeof(int) * (size_t)nm);
+    if (rc) return rc;
+    char *db = static_cast<char *>(c->dws);
+    BjMat *dmats = reinterpret_cast<BjMat *>(db + oMats);
+    int *dflags = reinterpret_cast<int *>(db + oFlags);
+    {
+        BjMat *hmats = static_cast<BjMat *>(c->hws);
+        for (int i = 0; i < nm; ++i) {
+            const int b = insts[i];
+            const HM &h = hm[i];
+            BjMat &B = hmats[i];
+            std::memset(&B, 0, sizeof B);
+            B.A = A[b];
+            B.W = db + h.oW;
+            B.V = db + h.oV;
+            B.S = S[b];
+            B.Uout = (U && U[b]) ? U[b] : nullptr;
+            B.Vout = (V && V[b]) ? V[b] : nullptr;
+            B.pair_state = reinterpret_cast<double *>(db + h.oPS);
+            B.M = h.M;
+            B.N = h.N;
+            B.NP = h.NP;
+            B.lda = lda[b];
+            B.ldu = B.Uout ? ldu[b] : 0;
+            B.ldv = B.Vout ? ldv[b] : 0;
+            B.trans = m[b] < n[b] ? 1 : 0;
+            B.inst = b;
+            B.ntask_state = h.nb * (h.nb - 1) / 2;
+        }
+        if ((rc = c->upload_to(oMats, sizeof(BjMat) * (size_t)nm))) return rc;
+    }
+    hipError_t e;
+    int pi = c->prof_begin(BSVD_STAGE_JACOBI);
+    e = launch_bj_init(dtype, dmats, nm, c->stream);
+    if (e != hipSuccess) return c->hip_fail(e, "block init launch");
+    c->prof_end(pi, 0.0, 0.0);
+
+    std::vector<int> active(nm);
+    for (int i = 0; i < nm; ++i) active[i] = i;
+    for (int sw = 0; sw < max_sweeps && !active.empty(); ++sw) {
+        for (int s = 0; s < nbmax - 1; ++s) {
+            // tasks of this step
+            if ((rc = c->ensure_host(dsz))) return rc;
+            char *hb = static_cast<char *>(c->hws);
+            Arena up;
+            size_t ntask = 0;
+            for (int i : active)
+                if (s < hm[i].nb - 1) ntask += hm[i].nb / 2;
+            if (ntask == 0) continue;
+            const size_t oT = up.alloc(sizeof(BjTask) * ntask);
+            const size_t oSD = up.alloc(sizeof(SvdDesc) * ntask);
+            const size_t oL = up.alloc(sizeof(int) * ntask);
+            if (up.off > dsz) return c->fail(BSVD_EHIP, "internal: block descriptor overflow");
+            BjTask *ht = reinterpret_cast<BjTask *>(hb + oT);
+            SvdDesc *hs = reinterpret_cast<SvdDesc *>(hb + oSD);
+            int *hl = reinterpret_cast<int *>(hb + oL);
+            size_t k = 0;
+            for (int i : active) {
+                const HM &h = hm[i];
+                if (s >= h.nb - 1) continue;
+                const int L = h.nb - 1;
+                for (int g = 0; g < h.nb / 2; ++g) {
+                    int p, q;
+                    if (g == 0) {
+                        p = s;
+                        q = L;
+                    } else {
+                        p = (s + g) % L;
+                        q = ((s - g) % L + L) % L;
+                    }
+                    BjTask &t = ht[k];
+                    t.mat = i;
+                    t.p = std::min(p, q);
+                    t.q = std::max(p, q);
+                    t.G = reinterpret_cast<double *>(db + h.oG) + (size_t)g * K * K;
+                    t.VG = reinterpret_cast<double *>(db + h.oVG) + (size_t)g * K * K;
+                    t.state = reinterpret_cast<double *>(db + h.oPS) + 2 * ((size_t)s * (h.nb / 2) + g);
+                    SvdDesc &d = hs[k];
+                    d.A = t.G;
+                    d.S = reinterpret_cast<double *>(db + h.oSg) + (size_t)g * K;
+                    d.U = nullptr;
+                    d.V = t.VG;
+                    d.m = K;
+                    d.n = K;
+                    d.lda = K;
+                    d.ldu = 0;
+                    d.ldv = K;
+                    d.trans = 0;
+                    d.M = K;
+                    d.N = K;
+                    hl[k] = (int)k;
+                    ++k;
+                }
+            }
+            if ((rc = c->upload(up.off))) return rc;
+            const BjTask *dt = reinterpret_cast<const BjTask *>(db + oT);
+            const SvdDesc *dsd = reinterpret_cast<const SvdDesc *>(db + oSD);
+            const int *dl = reinterpret_cast<const int *>(db + oL);
+            double gram_b = 0, gram_f = 0, app_b = 0, app_f = 0;
+            for (int i : active) {
+                const HM &h = hm[i];
+                if (s >= h.nb - 1) continue;
+                const double tasks_i = h.nb / 2;
+                gram_b += tasks_i * (double)esz * h.M * K;
+                gram_f += tasks_i * 2.0 * h.M * K * K;
+                app_b += tasks_i * 2.0 * (double)esz * (h.M + h.NP) * K;
+                app_f += tasks_i * 2.0 * (h.M + h.NP) * (double)K * K;
+            }
+            pi = c->prof_begin(BSVD_STAGE_SKETCH);
+            e = launch_bj_gram(dtype, w, dmats, dt, (int)ntask, tol, c->stream);
+            if (e != hipSuccess) return c->hip_fail(e, "block gram launch");
+            c->prof_end(pi, gram_b, gram_f);
+            pi = c->prof_begin(BSVD_STAGE_JACOBI);
+            JKey jk;
+            if (choose_jacobi(0, K, K, 0, &jk)) return c->fail(BSVD_EUNSUP, "internal: no Jacobi kernel for G");
+            if (jk.kind == JK_WAVE)
+                e = launch_jacobi_wave(0, jk.a, jk.b, dsd, dl, (int)ntask, 1e-15, 60, nullptr, nullptr, c->stream);
+            else
+                e = launch_jacobi_lds(0, jk.a, jk.b, dsd, dl, (int)ntask, 1e-15, 60, nullptr, nullptr, c->stream);
+            if (e != hipSuccess) return c->hip_fail(e, "block inner svd launch");
+            c->prof_end(pi, 0.0, 0.0);
+            pi = c->prof_begin(BSVD_STAGE_OUTPUT);
+            e = launch_bj_apply(dtype, w, dmats, dt, (int)ntask, c->stream);
+            if (e != hipSuccess) return c->hip_fail(e, "block apply launch");
+            c->prof_end(pi, app_b, app_f);
+        }
+        // convergence of the sweep
+        if ((rc = c->ensure_host(dsz))) return rc;
+        int *hl = static_cast<int *>(c->hws);
+        for (size_t i = 0; i < active.size(); ++i) hl[i] = active[i];
+        if ((rc = c->upload(sizeof(int) * active.size()))) return rc;
+        const int *dl = reinterpret_cast<const int *>(db);
+        pi = c->prof_begin(BSVD_STAGE_SMALL);
+        e = launch_bj_sweep(dmats, dl, (int)active.size(), tol, dflags, c->stream);
+        if (e != hipSuccess) return c->hip_fail(e, "block sweep launch");
+        c->prof_end(pi, 0.0, 0.0);
+        e = hipMemcpyAsync(c->rb, dflags, sizeof(int) * active.size(), hipMemcpyDeviceToHost, c->stream);
+        if (e != hipSuccess) return c->hip_fail(e, "hipMemcpyAsync(block flags)");
+        e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) return c->hip_fail(e, "hipStreamSynchronize");
+        const int *rb = static_cast<const int *>(c->rb);
+        std::vector<int> still, done;
+        for (size_t i = 0; i < active.size(); ++i) (rb[i] ? done : still).push_back(active[i]);
+        if (!done.empty()) {
+            if ((rc = c->ensure_host(dsz))) return rc;
+            int *hd = static_cast<int *>(c->hws);
+            std::copy(done.begin(), done.end(), hd);
+            if ((rc = c->upload(sizeof(int) * done.size()))) return rc;
+            e = launch_bj_mark_done(dmats, reinterpret_cast<const int *>(db), (int)done.size(), c->stream);
+            if (e != hipSuccess) return c->hip_fail(e, "block mark launch");
+        }
+        active.swap(still);
+    }
+    // outputs for every matrix
+    if ((rc = c->ensure_host(dsz))) return rc;
+    int *hl = static_cast<int *>(c->hws);
+    for (int i = 0; i < nm; ++i) hl[i] = i;
+    if ((rc = c->upload(sizeof(int) * (size_t)nm))) return rc;
+    pi = c->prof_begin(BSVD_STAGE_SMALL);
+    e = launch_bj_finalize(dtype, dmats, reinterpret_cast<const int *>(db), nm, nmax, sweeps, info, max_sweeps,
+                           c->stream);
+    if (e != hipSuccess) return c->hip_fail(e, "block finalize launch");
+    c->prof_end(pi, 0.0, 0.0);
+    return BSVD_OK;
+}
+
+}  // namespace bsvd

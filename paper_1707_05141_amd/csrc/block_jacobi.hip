@@ -1,0 +1,319 @@
+// One-sided block Jacobi in HBM, Gram path (Section 6.1, Algorithm 3), gfx950.
+//
+// The working matrix W (M x NP, NP = N rounded up to a multiple of 2w; zero padding) and the
+// accumulated rotations V (NP x NP) live in the workspace. Each outer sweep visits the block pairs
+// in round-robin order: at each step every matrix processes its NP/(2w) disjoint pairs of w-column
+// blocks, so a step is one launch of each kernel below over (matrix, pair) tasks:
+//   bj_gram_kernel   G = [W_p W_q]^T [W_p W_q] (K x K, K = 2w) on FP64 MFMA, plus the scaled
+//                    off-diagonal measure e = max |G_ab| / sqrt(G_aa G_bb) that tells whether the
+//                    pair needs a rotation (Algorithm 3's scaledOffdiag).
+//   (batched one-sided Jacobi SVD of every G, the wave / LDS kernels; the accumulated right
+//    rotations V_G are the block rotation, orthogonal by construction)
+//   bj_apply_kernel  [W_p W_q] <- [W_p W_q] V_G and [V_p V_q] <- [V_p V_q] V_G in place, FP64 MFMA.
+// Matrices whose every pair measure in a sweep is <= tol are done; bj_finalize_kernel then writes
+// sigma (column norms, descending), U (normalised columns) and V.
+//
+// MFMA fragment layout of v_mfma_f64_16x16x4f64 used here (wave64): lane l supplies A[l % 16][l / 16]
+// and B[l / 16][l % 16] for the 16x4 and 4x16 operands, and holds D[l / 16 + 4 r][l % 16] in
+// item r of the 4-element accumulator (checked on the device against a host product).
+
+#include "block_jacobi.hpp"
+#include "common.hpp"
+
+namespace bsvd {
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ d4_t mfma_f64(double a, double b, d4_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// W (M x NP col-major, ld M) <- A or A^T (zero padding), V <- I.
+template <typename T>
+__global__ __launch_bounds__(256) void bj_init_kernel(const BjMat *__restrict__ mats) {
+    const BjMat B = mats[blockIdx.y];
+    const size_t tot = (size_t)B.M * B.NP;
+    const T *A = static_cast<const T *>(B.A);
+    T *W = static_cast<T *>(B.W);
+    for (size_t idx = blockIdx.x * 256 + threadIdx.x; idx < tot; idx += (size_t)gridDim.x * 256) {
+        const int c = (int)(idx / B.M), r = (int)(idx - (size_t)c * B.M);
+        T v = T(0);
+        if (c < B.N) v = B.trans ? A[c + (size_t)r * B.lda] : A[r + (size_t)c * B.lda];
+        W[idx] = v;
+    }
+    T *V = static_cast<T *>(B.V);
+    const size_t vt = (size_t)B.NP * B.NP;
+    for (size_t idx = blockIdx.x * 256 + threadIdx.x; idx < vt; idx += (size_t)gridDim.x * 256) {
+        const int c = (int)(idx / B.NP), r = (int)(idx - (size_t)c * B.NP);
+        V[idx] = (r == c) ? T(1) : T(0);
+    }
+}
+
+// Column index of local column a (0..K-1) of task t: the first w columns are block p, the rest q.
+__device__ __forceinline__ int bj_col(const BjTask &t, int a, int w) { return a < w ? t.p * w + a : t.q * w + (a - w); }
+
+// G = Wpq^T Wpq with K = 2w; 256 threads = 4 waves; wave v computes output tiles (ti, tj) with
+// ti * (K/16) + tj == v (mod 4). Rows are staged in chunks of 16 through LDS (coalesced loads).
+template <typename T, int W_>
+__global__ __launch_bounds__(256) void bj_gram_kernel(const BjMat *__restrict__ mats, const BjTask *__restrict__ tasks,
+                                                      double tol) {
+    constexpr int K = 2 * W_;
+    constexpr int NT = K / 16;           // tiles per dimension
+    constexpr int TPW = NT * NT / 4 > 0 ? NT * NT / 4 : 1;  // tiles per wave
+    constexpr int RC = 16;               // rows per chunk
+    __shared__ double xs[RC][K + 1];
+    __shared__ double gsh[K][K + 1];
+    __shared__ double emax[256];
+    const BjTask t = tasks[blockIdx.x];
+    const BjMat B = mats[t.mat];
+    const T *W = static_cast<const T *>(B.W);
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, l = tid & 63;
+    d4_t acc[TPW];
+#pragma unroll
+    for (int i = 0; i < TPW; ++i) acc[i] = d4_t{0.0, 0.0, 0.0, 0.0};
+    for (int r0 = 0; r0 < B.M; r0 += RC) {
+        for (int idx = tid; idx < RC * K; idx += 256) {
+            const int a = idx / RC, rr = idx - (idx / RC) * RC;
+            const int r = r0 + rr;
+            xs[rr][a] = r < B.M ? (double)W[r + (size_t)bj_col(t, a, W_) * B.M] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < TPW; ++i) {
+            const int tile = wave + 4 * i;
+            if (tile < NT * NT) {
+                const int ti = tile / NT, tj = tile - (tile / NT) * NT;
+#pragma unroll
+                for (int k0 = 0; k0 < RC; k0 += 4) {
+                    // A = Wpq^T (rows = columns of Wpq), B = Wpq
+                    const double a = xs[k0 + l / 16][ti * 16 + (l % 16)];
+                    const double b = xs[k0 + l / 16][tj * 16 + (l % 16)];
+                    acc[i] = mfma_f64(a, b, acc[i]);
+                }
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < TPW; ++i) {
+        const int tile = wave + 4 * i;
+        if (tile < NT * NT) {
+            const int ti = tile / NT, tj = tile - (tile / NT) * NT;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) gsh[ti * 16 + (l / 16) + 4 * r][tj * 16 + (l % 16)] = acc[i][r];
+        }
+    }
+    __syncthreads();
+    // write G (K x K col-major) and the scaled off-diagonal measure
+    double *G = t.G;
+    double e = 0.0;
+    for (int idx = tid; idx < K * K; idx += 256) {
+        const int b = idx / K, a = idx - (idx / K) * K;
+        const double g = gsh[a][b];
+        G[idx] = g;
+        if (a < b) {
+            const double d = gsh[a][a] * gsh[b][b];
+            if (d > 0.0) e = fmax(e, fabs(g) / sqrt(d));
+        }
+    }
+    emax[tid] = e;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (tid < s) emax[tid] = fmax(emax[tid], emax[tid + s]);
+        __syncthreads();
+    }
+    if (tid == 0) {
+        t.state[0] = emax[0];            // measure of this pair
+        t.state[1] = emax[0] > tol ? 1.0 : 0.0;
+    }
+}
+
+// [X_p X_q] <- [X_p X_q] V_G for X = W (M rows) and X = V (NP rows), in place. Each wave owns
+// 16-row tiles: it reads the tile's K columns, multiplies by V_G (staged in LDS) on MFMA, and
+// writes the tile back after all of its reads.
+template <typename T, int W_>
+__global__ __launch_bounds__(256) void bj_apply_kernel(const BjMat *__restrict__ mats, const BjTask *__restrict__ tasks) {
+    constexpr int K = 2 * W_;
+    constexpr int NT = K / 16;
+    __shared__ double vg[K][K + 1];
+    const BjTask t = tasks[blockIdx.x];
+    if (t.state[1] == 0.0) return;  // pair already orthogonal to tolerance
+    const BjMat B = mats[t.mat];
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, l = tid & 63;
+    for (int idx = tid; idx < K * K; idx += 256) {
+        const int b = idx / K, a = idx - (idx / K) * K;
+        vg[a][b] = t.VG[idx];
+    }
+    __syncthreads();
+    for (int which = 0; which < 2; ++which) {
+        T *X = static_cast<T *>(which == 0 ? B.W : B.V);
+        const int rows = which == 0 ? B.M : B.NP;
+        const int ntile = (rows + 15) / 16;
+        for (int rt = wave; rt < ntile; rt += 4) {
+            const int r = rt * 16 + (l % 16);
+            const bool rok = r < rows;
+            d4_t acc[NT];
+#pragma unroll
+            for (int j = 0; j < NT; ++j) acc[j] = d4_t{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int k0 = 0; k0 < K; k0 += 4) {
+                const int kk = k0 + l / 16;
+                const double a = rok ? (double)X[r + (size_t)bj_col(t, kk, W_) * rows] : 0.0;
+#pragma unroll
+                for (int j = 0; j < NT; ++j) acc[j] = mfma_f64(a, vg[kk][j * 16 + (l % 16)], acc[j]);
+            }
+            // lane holds rows l/16 + 4 q of output column j*16 + l%16 of this row tile
+#pragma unroll
+            for (int j = 0; j < NT; ++j) {
+                const int col = bj_col(t, j * 16 + (l % 16), W_);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int rr = rt * 16 + (l / 16) + 4 * q;
+                    if (rr < rows) X[rr + (size_t)col * rows] = (T)acc[j][q];
+                }
+            }
+        }
+    }
+}
+
+// Per matrix: maximum pair measure of the sweep -> done flag.
+__global__ void bj_sweep_kernel(BjMat *__restrict__ mats, const int *__restrict__ list, int count, double tol,
+                                int *__restrict__ flags) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    BjMat &B = mats[list[i]];
+    double e = 0.0;
+    for (int s = 0; s < B.ntask_state; ++s) e = fmax(e, B.pair_state[2 * s]);
+    B.sweeps += 1;
+    flags[i] = e <= tol ? 1 : 0;
+}
+
+// sigma = column norms, descending (stable); U = normalised columns of W, V = accumulated rotations.
+template <typename T>
+__global__ __launch_bounds__(256) void bj_finalize_kernel(const BjMat *__restrict__ mats, const int *__restrict__ list,
+                                                          int *__restrict__ sweeps_out, int *__restrict__ info_out,
+                                                          int max_sweeps) {
+    extern __shared__ double sh[];
+    const int mi = list[blockIdx.x];
+    const BjMat B = mats[mi];
+    double *nrm = sh;
+    int *rk = reinterpret_cast<int *>(sh + B.N);
+    const T *W = static_cast<const T *>(B.W);
+    const T *V = static_cast<const T *>(B.V);
+    const int tid = threadIdx.x;
+    for (int c = tid; c < B.N; c += 256) {
+        double s = 0.0;
+        for (int r = 0; r < B.M; ++r) s = fma((double)W[r + (size_t)c * B.M], (double)W[r + (size_t)c * B.M], s);
+        nrm[c] = sqrt(s);
+    }
+    __syncthreads();
+    for (int c = tid; c < B.N; c += 256) {
+        const double sc = nrm[c];
+        int rank = 0;
+        for (int q = 0; q < B.N; ++q) {
+            const double sq = nrm[q];
+            rank += (sq > sc || (sq == sc && q < c)) ? 1 : 0;
+        }
+        rk[c] = rank;
+    }
+    __syncthreads();
+    T *S = static_cast<T *>(B.S);
+    T *Lf = static_cast<T *>(B.trans ? B.Vout : B.Uout);
+    const int ldl = B.trans ? B.ldv : B.ldu;
+    T *Rf = static_cast<T *>(B.trans ? B.Uout : B.Vout);
+    const int ldr = B.trans ? B.ldu : B.ldv;
+    for (int c = tid; c < B.N; c += 256) S[rk[c]] = (T)nrm[c];
+    for (int c = 0; c < B.N; ++c) {
+        const int r0 = rk[c];
+        if (Lf) {
+            const double inv = nrm[c] > 0.0 ? 1.0 / nrm[c] : 0.0;
+            for (int r = tid; r < B.M; r += 256) Lf[r + (size_t)r0 * ldl] = (T)((double)W[r + (size_t)c * B.M] * inv);
+        }
+        if (Rf)
+            for (int r = tid; r < B.N; r += 256) Rf[r + (size_t)r0 * ldr] = V[r + (size_t)c * B.NP];
+    }
+    if (tid == 0) {
+        if (sweeps_out) sweeps_out[B.inst] = B.sweeps;
+        if (info_out) info_out[B.inst] = B.done ? INFO_OK : INFO_SWEEPS;
+    }
+    (void)max_sweeps;
+}
+
+__global__ void bj_mark_done_kernel(BjMat *__restrict__ mats, const int *__restrict__ list, int count) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) mats[list[i]].done = 1;
+}
+
+// ---------------------------------------------------------------------------------------------
+hipError_t launch_bj_init(int dtype, const BjMat *mats, int nmat, hipStream_t st) {
+    if (nmat <= 0) return hipSuccess;
+    if (dtype == 0)
+        hipLaunchKernelGGL(bj_init_kernel<double>, dim3(64, nmat), dim3(256), 0, st, mats);
+    else
+        hipLaunchKernelGGL(bj_init_kernel<float>, dim3(64, nmat), dim3(256), 0, st, mats);
+    return hipGetLastError();
+}
+
+hipError_t launch_bj_gram(int dtype, int w, const BjMat *mats, const BjTask *tasks, int ntask, double tol,
+                          hipStream_t st) {
+    if (ntask <= 0) return hipSuccess;
+#define BJ_G(WW)                                                                                       \
+    if (w == WW) {                                                                                     \
+        if (dtype == 0)                                                                                \
+            hipLaunchKernelGGL((bj_gram_kernel<double, WW>), dim3(ntask), dim3(256), 0, st, mats, tasks, tol); \
+        else                                                                                           \
+            hipLaunchKernelGGL((bj_gram_kernel<float, WW>), dim3(ntask), dim3(256), 0, st, mats, tasks, tol);  \
+        return hipGetLastError();                                                                      \
+    }
+    BJ_G(8)
+    BJ_G(16)
+    BJ_G(32)
+#undef BJ_G
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_bj_apply(int dtype, int w, const BjMat *mats, const BjTask *tasks, int ntask, hipStream_t st) {
+    if (ntask <= 0) return hipSuccess;
+#define BJ_A(WW)                                                                                       \
+    if (w == WW) {                                                                                     \
+        if (dtype == 0)                                                                                \
+            hipLaunchKernelGGL((bj_apply_kernel<double, WW>), dim3(ntask), dim3(256), 0, st, mats, tasks); \
+        else                                                                                           \
+            hipLaunchKernelGGL((bj_apply_kernel<float, WW>), dim3(ntask), dim3(256), 0, st, mats, tasks);  \
+        return hipGetLastError();                                                                      \
+    }
+    BJ_A(8)
+    BJ_A(16)
+    BJ_A(32)
+#undef BJ_A
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_bj_sweep(BjMat *mats, const int *list, int count, double tol, int *flags, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(bj_sweep_kernel, dim3((count + 255) / 256), dim3(256), 0, st, mats, list, count, tol, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_bj_mark_done(BjMat *mats, const int *list, int count, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(bj_mark_done_kernel, dim3((count + 255) / 256), dim3(256), 0, st, mats, list, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_bj_finalize(int dtype, const BjMat *mats, const int *list, int count, int nmax, int *sweeps,
+                              int *info, int max_sweeps, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    const size_t sh = (sizeof(double) + sizeof(int)) * (size_t)nmax + 16;
+    if (dtype == 0)
+        hipLaunchKernelGGL(bj_finalize_kernel<double>, dim3(count), dim3(256), sh, st, mats, list, sweeps, info,
+                           max_sweeps);
+    else
+        hipLaunchKernelGGL(bj_finalize_kernel<float>, dim3(count), dim3(256), sh, st, mats, list, sweeps, info,
+                           max_sweeps);
+    return hipGetLastError();
+}
+
+}  // namespace bsvd

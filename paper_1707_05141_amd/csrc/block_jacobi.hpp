@@ -1,0 +1,37 @@
+// Descriptors and launchers of the one-sided block Jacobi (Gram path).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace bsvd {
+
+// One matrix of the block-Jacobi path (device resident).
+struct BjMat {
+    const void *A;  // caller's input
+    void *W;        // working matrix M x NP (ld M)
+    void *V;        // accumulated rotations NP x NP (ld NP)
+    void *S, *Uout, *Vout;
+    double *pair_state;  // 2 doubles per block pair of a sweep: measure, rotate flag
+    int M, N, NP, lda, ldu, ldv, trans, inst;
+    int ntask_state;     // block pairs per sweep
+    int sweeps, done;
+};
+
+// One (matrix, block pair) task of a round-robin step.
+struct BjTask {
+    double *G;      // K x K Gram matrix (ld K)
+    double *VG;     // K x K block rotation (ld K)
+    double *state;  // this pair's slot in the matrix's pair_state
+    int mat, p, q, pad;
+};
+
+hipError_t launch_bj_init(int dtype, const BjMat *mats, int nmat, hipStream_t st);
+hipError_t launch_bj_gram(int dtype, int w, const BjMat *mats, const BjTask *tasks, int ntask, double tol,
+                          hipStream_t st);
+hipError_t launch_bj_apply(int dtype, int w, const BjMat *mats, const BjTask *tasks, int ntask, hipStream_t st);
+hipError_t launch_bj_sweep(BjMat *mats, const int *list, int count, double tol, int *flags, hipStream_t st);
+hipError_t launch_bj_mark_done(BjMat *mats, const int *list, int count, hipStream_t st);
+hipError_t launch_bj_finalize(int dtype, const BjMat *mats, const int *list, int count, int nmax, int *sweeps,
+                              int *info, int max_sweeps, hipStream_t st);
+
+}  // namespace bsvd

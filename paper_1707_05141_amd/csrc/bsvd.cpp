@@ -225,7 +225,6 @@ int batched_svd(bsvd_ctx *ctx, int dtype, int batch, const int *m, const int *n,
         return c->fail(BSVD_EARG, "FORCE_WAVE and FORCE_LDS are exclusive");
     if ((flags & BSVD_SVD_QR_FIRST) && (flags & BSVD_SVD_NO_QR))
         return c->fail(BSVD_EARG, "QR_FIRST and NO_QR are exclusive");
-    if (flags & BSVD_SVD_FORCE_BLOCK) return c->fail(BSVD_EUNSUP, "block Jacobi path is not available");
     if (tol <= 0.0) tol = (dtype == BSVD_F64) ? 1e-15 : 1e-6;
     if (max_sweeps <= 0) max_sweeps = 60;
     hipError_t e = hipSetDevice(c->device);
@@ -236,6 +235,8 @@ int batched_svd(bsvd_ctx *ctx, int dtype, int batch, const int *m, const int *n,
     std::vector<int> use_qr(batch, 0);
     std::vector<JKey> jkey(batch);
     std::vector<QKey> qkey(batch);
+    std::vector<int> blk;  // instances on the block-Jacobi path
+    std::vector<char> is_blk(batch, 0);
     int nqr = 0;
     for (int b = 0; b < batch; ++b) {
         if (m[b] < 1) return c->fail(BSVD_EARG, "instance %d: m = %d < 1", b, m[b]);
@@ -247,6 +248,11 @@ int batched_svd(bsvd_ctx *ctx, int dtype, int batch, const int *m, const int *n,
         if (V && V[b] && ldv[b] < n[b]) return c->fail(BSVD_EARG, "instance %d: ldv = %d < n = %d", b, ldv[b], n[b]);
         const int M = m[b] >= n[b] ? m[b] : n[b];
         const int N = m[b] >= n[b] ? n[b] : m[b];
+        if (flags & BSVD_SVD_FORCE_BLOCK) {
+            is_blk[b] = 1;
+            blk.push_back(b);
+            continue;
+        }
         bool qr = false;
         if (!(flags & BSVD_SVD_NO_QR) && ((flags & BSVD_SVD_QR_FIRST) || M > N)) {
             int nb, sg, kr;
@@ -260,8 +266,24 @@ int batched_svd(bsvd_ctx *ctx, int dtype, int batch, const int *m, const int *n,
         use_qr[b] = qr ? 1 : 0;
         nqr += qr ? 1 : 0;
         int rc = choose_jacobi(dtype, qr ? N : M, N, flags, &jkey[b]);
-        if (rc) return c->fail(rc, "instance %d: %d x %d has no Jacobi kernel for the requested path", b, m[b], n[b]);
+        if (rc) {
+            if (flags & (BSVD_SVD_FORCE_WAVE | BSVD_SVD_FORCE_LDS | BSVD_SVD_QR_FIRST))
+                return c->fail(rc, "instance %d: %d x %d has no Jacobi kernel for the requested path", b, m[b], n[b]);
+            // too large for registers / LDS: one-sided block Jacobi in HBM
+            use_qr[b] = 0;
+            nqr -= qr ? 1 : 0;
+            is_blk[b] = 1;
+            blk.push_back(b);
+        }
     }
+    int bw = 16;
+    if (flags & BSVD_SVD_BLOCK_W8) bw = 8;
+    if (flags & BSVD_SVD_BLOCK_W32) bw = 32;
+    if (!blk.empty()) {
+        int rc = block_jacobi_run(c, dtype, bw, blk, m, n, A, lda, S, U, ldu, V, ldv, tol, max_sweeps, sweeps, info);
+        if (rc) return rc;
+    }
+    if ((int)blk.size() == batch) return BSVD_OK;
 
     // ---- workspace layout: [descriptors + lists | per-instance intermediates] ------------
     Arena up;
@@ -275,7 +297,7 @@ int batched_svd(bsvd_ctx *ctx, int dtype, int batch, const int *m, const int *n,
     wk.off = up.off;
     std::vector<size_t> o_q(batch, 0), o_r(batch, 0), o_ur(batch, 0);
     for (int b = 0; b < batch; ++b) {
-        if (!use_qr[b]) continue;
+        if (!use_qr[b] || is_blk[b]) continue;
         const size_t M = m[b] >= n[b] ? m[b] : n[b];
         const size_t N = m[b] >= n[b] ? n[b] : m[b];
         o_q[b] = wk.alloc(esz * M * N);
@@ -294,6 +316,7 @@ int batched_svd(bsvd_ctx *ctx, int dtype, int batch, const int *m, const int *n,
     GemmDesc *gd = reinterpret_cast<GemmDesc *>(hb + o_gd);
     int qi = 0;
     for (int b = 0; b < batch; ++b) {
+        if (is_blk[b]) continue;
         const int trans0 = m[b] < n[b] ? 1 : 0;
         const int M = trans0 ? n[b] : m[b];
         const int N = trans0 ? m[b] : n[b];
@@ -365,6 +388,7 @@ int batched_svd(bsvd_ctx *ctx, int dtype, int batch, const int *m, const int *n,
     std::vector<int> glist;
     qi = 0;
     for (int b = 0; b < batch; ++b) {
+        if (is_blk[b]) continue;
         jb[jkey[b]].push_back(b);
         if (use_qr[b]) {
             qb[qkey[b]].push_back(qi);
@@ -400,6 +424,7 @@ int batched_svd(bsvd_ctx *ctx, int dtype, int batch, const int *m, const int *n,
     const int *dgl = reinterpret_cast<const int *>(db + o_gl);
     double qr_fl = 0.0, qr_by = 0.0, j_by = 0.0, g_fl = 0.0, g_by = 0.0;
     for (int b = 0; b < batch; ++b) {
+        if (is_blk[b]) continue;
         const double M = m[b] >= n[b] ? m[b] : n[b], N = m[b] >= n[b] ? n[b] : m[b];
         j_by += esz * (use_qr[b] ? N * N : M * N) + esz * (M * N + N * N + N);
         if (use_qr[b]) {

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 namespace bsvd {
 
 // Per-instance descriptor of a batched_svd call, uploaded to the device workspace.
@@ -51,5 +53,10 @@ bool jacobi_lds_supported(int dtype, int M, int N, int *mmax, int *nmax);
 hipError_t launch_jacobi_lds(int dtype, int mmax, int nmax, const SvdDesc *d, const int *list, int count, double tol,
                              int max_sweeps, int *sweeps, int *info, hipStream_t st);
 hipError_t launch_gemm_small(int dtype, const GemmDesc *d, const int *list, int count, hipStream_t st);
+
+struct Ctx;
+int block_jacobi_run(Ctx *c, int dtype, int w, const std::vector<int> &insts, const int *m, const int *n,
+                     const void *const *A, const int *lda, void *const *S, void *const *U, const int *ldu,
+                     void *const *V, const int *ldv, double tol, int max_sweeps, int *sweeps, int *info);
 
 }  // namespace bsvd
