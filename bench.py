@@ -299,7 +299,7 @@ def run_c3(args, torch, P, synth):
     b, m, n = 500, 512, 256
     sig = synth.graded_sigma_log(n, 10.0)
     A_np = synth.batch_prescribed(b, m, n, sig, seed=3)
-    flags = _lib.SVD_FORCE_BLOCK | {8: _lib.SVD_BLOCK_W8, 16: 0, 32: _lib.SVD_BLOCK_W32}[args.block_w]
+    flags = _lib.SVD_FORCE_BLOCK | {0: 0, 8: _lib.SVD_BLOCK_W8, 16: _lib.SVD_BLOCK_W16, 32: _lib.SVD_BLOCK_W32}[args.block_w]
     out = {}
     for dt, name in ((torch.float64, "f64"), (torch.float32, "f32")):
         A = torch.from_numpy(A_np).to(device="cuda", dtype=dt)
@@ -335,7 +335,8 @@ def run_c3(args, torch, P, synth):
     achieved = gram["flops"] / (gram["ms"] * 1e-3) / 1e12
     point_flops = 9.0e9 * b  # point-Jacobi reference: 36 sweeps x 32,640 pairs x 7,680 flops per matrix
     res = dict(value=b / (f64["ms"] * 1e-3), unit="SVDs/s", ms_per_step=f64["ms"], dtype="f64",
-               config=dict(workload="block_jacobi_500x512x256_kappa1e10", batch=b, block_w=args.block_w,
+               config=dict(workload="block_jacobi_500x512x256_kappa1e10", batch=b,
+                           block_w=args.block_w or P.tune_get(0, 0, m, n), block_w_f32=args.block_w or P.tune_get(0, 1, m, n),
                            f64=dict(ms=f64["ms"], sweeps=f64["mean_block_sweeps"], max_sigma_err=f64["max_sigma_err"]),
                            f32=dict(ms=out["f32"]["ms"], sweeps=out["f32"]["mean_block_sweeps"],
                                     max_sigma_err=out["f32"]["max_sigma_err"], info_max=out["f32"]["info_max"]),
@@ -357,7 +358,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c1", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
-    ap.add_argument("--block-w", type=int, default=16, choices=(8, 16, 32))
+    ap.add_argument("--block-w", type=int, default=0, choices=(0, 8, 16, 32), help="0 = autotuned")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on exactly one GPU; --gpus %d is not supported "

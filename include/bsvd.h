@@ -50,13 +50,15 @@ enum {
     BSVD_SVD_QR_FIRST = 1u << 3,    /* Householder QR first, then Jacobi of R (also for square inputs) */
     BSVD_SVD_NO_QR = 1u << 4,       /* never run the QR pre-step (default: QR first when m != n) */
     BSVD_SVD_JACOBI_ON_R = 1u << 5, /* after QR, rotate the columns of R instead of its rows */
-    BSVD_SVD_BLOCK_W8 = 1u << 6,    /* block Jacobi with 8-column blocks (default 16) */
-    BSVD_SVD_BLOCK_W32 = 1u << 7    /* block Jacobi with 32-column blocks */
+    BSVD_SVD_BLOCK_W8 = 1u << 6,    /* block Jacobi with 8-column blocks */
+    BSVD_SVD_BLOCK_W32 = 1u << 7,   /* block Jacobi with 32-column blocks */
+    BSVD_SVD_BLOCK_W16 = 1u << 8    /* block Jacobi with 16-column blocks (no flag: autotuned) */
 };
 
 /* Flags for batched_rsvd. */
 enum {
-    BSVD_RSVD_FIXED = 1u << 0 /* exactly ell0[b] samples, no adaptive growth (Algorithm 4 as printed) */
+    BSVD_RSVD_FIXED = 1u << 0,  /* exactly ell0[b] samples, no adaptive growth (Algorithm 4 as printed) */
+    BSVD_RSVD_LEARNED = 1u << 1 /* initial sample count from the context's rank model */
 };
 
 /* Create a context bound to `device` (HIP ordinal) and `stream` (a hipStream_t; NULL = the null
@@ -94,6 +96,19 @@ int bsvd_profile_enable(bsvd_ctx *ctx, int on);
  * algorithmic bytes (inputs read once + outputs written once) and flops, and the number of
  * launch groups; all output arrays have `nstage` entries (nullable). Clears the records. */
 int bsvd_profile_read(bsvd_ctx *ctx, int nstage, double *ms, double *bytes, double *flops, int *launches);
+
+/* Autotuner cache. Without a BSVD_SVD_BLOCK_W* flag, the first batched_svd call that sends a
+ * (dtype, M, N) class (M = max(m, n), N = min(m, n)) to the block path times widths 8, 16 and 32 on up
+ * to 128 of its instances and keeps the fastest in the context (kind 0).
+ *   bsvd_tune_get   value chosen for (kind, dtype, M, N) and up to max_cand (candidate, ms) pairs
+ *                   (host arrays, nullable); BSVD_EARG if the class was never tuned
+ *   bsvd_tune_save  write the cache as text lines "kind dtype M N value"
+ *   bsvd_tune_load  merge such a file into the context's cache (entries that name an unsupported
+ *                   width are skipped) */
+int bsvd_tune_get(bsvd_ctx *ctx, int kind, int dtype, int M, int N, int *value, float *times_ms, int *candidates,
+                  int max_cand);
+int bsvd_tune_save(const bsvd_ctx *ctx, const char *path);
+int bsvd_tune_load(bsvd_ctx *ctx, const char *path);
 
 /* Library version string. */
 const char *bsvd_version(void);
@@ -188,8 +203,12 @@ int batched_qr(bsvd_ctx *ctx, int dtype, int batch, const int *m, const int *n, 
  *   info         nullable DEVICE int[batch]: 0, 1 (Jacobi sweep cap), 2 (tolerance not met within
  *                the basis cap, or rank > max_rank), 3 (non-finite input; rank 0)
  *   seed         64-bit key of the sampling matrix
- *   flags        BSVD_RSVD_* (0 = adaptive)
+ *   flags        BSVD_RSVD_* (0 = adaptive). With BSVD_RSVD_LEARNED (ell0 must be NULL) the context's
+ *                rank model predicts each block's rank k^ from its probe features (bsvd_rank_features)
+ *                and the first block takes ell0 = ceil(k^ + margin) samples; the check and the
+ *                adaptive growth above remain the fallback whenever that basis is not accurate enough.
  *   ell0         nullable host int[batch]: initial number of samples (clamped to the basis cap)
+ *   samples      nullable DEVICE int[batch]: final basis size (number of Gaussian samples used)
  * The call synchronises its stream once per growth round and once per check (the per-instance
  * decisions are read back to plan the next round). Returns BSVD_OK, BSVD_EARG, BSVD_EUNSUP,
  * BSVD_ENOMEM or BSVD_EHIP.
@@ -197,7 +216,41 @@ int batched_qr(bsvd_ctx *ctx, int dtype, int batch, const int *m, const int *n, 
 int batched_rsvd(bsvd_ctx *ctx, int batch, const int *m, const int *n, const void *const *A, const int *lda,
                  const double *eps, const int *max_rank, void *const *S, void *const *U, const int *ldu,
                  void *const *V, const int *ldv, int *rank, double *err_est, int *info, unsigned long long seed,
-                 unsigned flags, const int *ell0);
+                 unsigned flags, const int *ell0, int *samples);
+
+/*
+ * Rank-prediction network (learned part). A 16 -> 64 -> 64 -> 1 MLP with ReLU hidden layers in FP32,
+ * 5,313 parameters, held in the context (parameter layout: W1[64][16], b1[64], W2[64][64], b2[64],
+ * W3[64], b3, output-major). It maps a block's 16 probe features to its predicted rank / 16 at the
+ * tolerance it was trained for; batched_rsvd with BSVD_RSVD_LEARNED turns that into the first
+ * sample count. Trained on the GPU by the library's own forward / backward / Adam kernels.
+ *
+ * bsvd_rank_features   DEVICE float[batch][16] features of each block: a probe sketch
+ *                      Y = A Omega_p with 16 Gaussian columns (counter columns 2^20 ..), R = qr(Y),
+ *                      f0 = log2(m)/9, f1 = log2(n)/9, f(1+i) = max(log10(|R_ii|/|R_00|), -20)/16 for
+ *                      i = 1..14 (-20/16 beyond min(16, m, n) columns). Shapes as batched_rsvd.
+ * bsvd_rank_model_init     He-uniform weights, zero biases, Adam state reset (seeded)
+ * bsvd_rank_model_set/get  parameters from / to a HOST float[5313]; margin added to 16 * prediction
+ * bsvd_rank_model_save/load  binary file: "BSVDMLP1", int 5313, float margin, 5313 floats
+ * bsvd_rank_model_forward  y[i] = f(X[i]) for DEVICE X[n][16], y[n]
+ * bsvd_rank_model_loss_grad  L = mean (f(X_i) - T_i)^2 (HOST *loss, nullable; synchronises) and
+ *                      dL/dparams into DEVICE grad[5313] (nullable: internal buffer)
+ * bsvd_rank_model_train    `epochs` passes over DEVICE (X, T) in shuffled mini-batches of `batch`,
+ *                      Adam (beta 0.9 / 0.999) with step lr; HOST *final_loss (nullable) is the loss
+ *                      over all n samples afterwards. Seeded, deterministic.
+ */
+int bsvd_rank_features(bsvd_ctx *ctx, int batch, const int *m, const int *n, const void *const *A, const int *lda,
+                       unsigned long long seed, float *feats);
+int bsvd_rank_model_nparam(void);
+int bsvd_rank_model_init(bsvd_ctx *ctx, unsigned long long seed);
+int bsvd_rank_model_set(bsvd_ctx *ctx, const float *params, float margin);
+int bsvd_rank_model_get(bsvd_ctx *ctx, float *params, float *margin);
+int bsvd_rank_model_save(bsvd_ctx *ctx, const char *path);
+int bsvd_rank_model_load(bsvd_ctx *ctx, const char *path);
+int bsvd_rank_model_forward(bsvd_ctx *ctx, int n, const float *X, float *y);
+int bsvd_rank_model_loss_grad(bsvd_ctx *ctx, int n, const float *X, const float *T, float *loss, float *grad);
+int bsvd_rank_model_train(bsvd_ctx *ctx, int n, const float *X, const float *T, int epochs, int batch, float lr,
+                          unsigned long long seed, float *final_loss);
 
 /*
  * bsvd_sample_omega -- write columns col0 .. col0+b-1 of instance `inst`'s Gaussian sampling matrix

@@ -66,6 +66,7 @@ def _load():
                                               ctypes.c_int, _D, _D, _D, _I, _I]
     lib.oracle_batched_qr.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _D, _D, _D, _I]
     lib.oracle_num_threads.restype = ctypes.c_int
+    lib.oracle_features.argtypes = [ctypes.c_int, ctypes.c_int, _D, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint32, _D]
     _lib = lib
     return lib
 
@@ -248,3 +249,13 @@ def mlp_loss_grad(params, X, y):
 
 def num_threads():
     return _load().oracle_num_threads()
+
+
+def features(A, seed, inst=0):
+    """The 16 probe features of a block (inputs of the rank network)."""
+    lib = _load()
+    A = _f64(A)
+    m, n = A.shape
+    f = np.zeros(16)
+    lib.oracle_features(m, n, _dp(A), m, int(seed) & (2**64 - 1), inst, _dp(f))
+    return f

@@ -24,6 +24,8 @@
  *                        sampling matrix; the counter generator is Philox4x32-10 of Salmon, Moraes,
  *                        Dror, Shaw, SC'11, and the Gaussian map is Box-Muller).
  *   oracle_mlp_*         Reference forward/backward of the 16-64-64-1 ReLU rank-prediction network.
+ *   oracle_features      Reference probe features that feed the network (probe sketch, QR, log decay
+ *                        of |R_ii|); the same definition the library documents for its features.
  *
  * Readings where the paper is silent (each listed in the design notes of the repository):
  *   - house(): beta = -sign(alpha)*||x|| with sign(0)=+1; a length-1 or already-zero sub-column
@@ -583,6 +585,37 @@ double oracle_mlp_loss_grad(int N, const double *p, const double *X, const doubl
         }
     }
     return loss / (double)N;
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Probe features of a block (inputs of the rank-prediction network): the probe sketch          */
+/* Y = A Omega_p with kp = min(16, m, n) Gaussian columns at counter columns 2^20 .. 2^20+kp-1,  */
+/* R = qr(Y) (Householder, above), and                                                          */
+/*   f0 = log2(m)/9, f1 = log2(n)/9, f(1+i) = max(log10(|R_ii|/|R_00|), -20)/16, i = 1..14,     */
+/* with -20/16 where i >= kp or R_00 = 0.                                                        */
+/* ------------------------------------------------------------------------------------------ */
+void oracle_features(int m, int n, const double *A, int lda, uint64_t seed, uint32_t inst, double *f) {
+    int kp = 16;
+    if (m < kp) kp = m;
+    if (n < kp) kp = n;
+    double *Y = (double *)malloc(sizeof(double) * (size_t)m * kp);
+    double *R = (double *)malloc(sizeof(double) * (size_t)kp * kp);
+    sketch(m, n, A, lda, seed, inst, 1 << 20, kp, Y, m);
+    oracle_qr(m, kp, Y, m, NULL, m, R, kp);
+    f[0] = log2((double)m) / 9.0;
+    f[1] = log2((double)n) / 9.0;
+    double r0 = fabs(R[0]);
+    for (int i = 1; i < 15; ++i) {
+        double v = -20.0;
+        if (i < kp && r0 > 0.0) {
+            double ri = fabs(R[i + (size_t)i * kp]);
+            v = ri > 0.0 ? log10(ri / r0) : -20.0;
+            if (v < -20.0) v = -20.0;
+        }
+        f[1 + i] = v / 16.0;
+    }
+    free(Y);
+    free(R);
 }
 
 /* ------------------------------------------------------------------------------------------ */

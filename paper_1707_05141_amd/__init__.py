@@ -85,7 +85,7 @@ def batched_qr(m, n, A_ptrs, lda, Q_ptrs=None, ldq=None, R_ptrs=None, ldr=None, 
 
 
 def batched_rsvd(m, n, A_ptrs, lda, max_rank, S_ptrs, U_ptrs=None, ldu=None, V_ptrs=None, ldv=None, *, eps=None,
-                 rank=None, err_est=None, info=None, seed=0, flags=0, ell0=None, device=None):
+                 rank=None, err_est=None, info=None, seed=0, flags=0, ell0=None, samples=None, device=None):
     """Direct mirror of the C entry point ``batched_rsvd`` (host shape / eps / max_rank / ell0 arrays,
     host arrays of device pointers, device tensors for rank / err_est / info)."""
     L = _lib.lib()
@@ -107,7 +107,8 @@ def batched_rsvd(m, n, A_ptrs, lda, max_rank, S_ptrs, U_ptrs=None, ldu=None, V_p
                         _lib.as_ip(max_rank), _lib.as_vp(S_ptrs), _lib.as_vp(U_ptrs), _lib.as_ip(ldu),
                         _lib.as_vp(V_ptrs), _lib.as_ip(ldv), None if rank is None else ctypes_ptr(rank),
                         None if err_est is None else ctypes_ptr(err_est), None if info is None else ctypes_ptr(info),
-                        int(seed) & (2 ** 64 - 1), int(flags), _lib.as_ip(ell0))
+                        int(seed) & (2 ** 64 - 1), int(flags), _lib.as_ip(ell0),
+                        None if samples is None else ctypes_ptr(samples))
     ctx.check(rc)
 
 
@@ -138,6 +139,29 @@ def profile_read(device=None):
     ctx.check(_lib.lib().bsvd_profile_read(ctx.h, ns, _lib.as_dp(ms), _lib.as_dp(by), _lib.as_dp(fl), _lib.as_ip(la)))
     return {name: dict(ms=float(ms[i]), bytes=float(by[i]), flops=float(fl[i]), launches=int(la[i]))
             for i, name in enumerate(_lib.STAGES)}
+
+
+def tune_get(kind, dtype, M, N, device=None):
+    """(value, {candidate: ms}) chosen by the autotuner for a shape class, or None if never tuned."""
+    import ctypes
+    ctx = _ctx(device if device is not None else torch.cuda.current_device())
+    v = ctypes.c_int(0)
+    t = (ctypes.c_float * 8)()
+    cnd = (ctypes.c_int * 8)()
+    rc = _lib.lib().bsvd_tune_get(ctx.h, int(kind), int(dtype), int(M), int(N), ctypes.byref(v), t, cnd, 8)
+    if rc != 0:
+        return None
+    return v.value, {cnd[i]: t[i] for i in range(8) if cnd[i]}
+
+
+def tune_save(path, device=None):
+    ctx = _ctx(device if device is not None else torch.cuda.current_device())
+    ctx.check(_lib.lib().bsvd_tune_save(ctx.h, str(path).encode()))
+
+
+def tune_load(path, device=None):
+    ctx = _ctx(device if device is not None else torch.cuda.current_device())
+    ctx.check(_lib.lib().bsvd_tune_load(ctx.h, str(path).encode()))
 
 
 def ctypes_ptr(t: torch.Tensor):
@@ -230,11 +254,89 @@ def rsvd_packed(buf, offs, m, n, *, eps=1e-6, max_rank=64, seed=0, flags=0, ell0
     rank = torch.zeros(b, dtype=torch.int32, device=dev)
     err = torch.zeros(b, dtype=torch.float64, device=dev)
     info = torch.zeros(b, dtype=torch.int32, device=dev)
+    samples = torch.zeros(b, dtype=torch.int32, device=dev)
     if b:
         A_ptrs = buf.data_ptr() + es * offs.astype(np.uint64)
         S_ptrs = S.data_ptr() + 8 * S.shape[1] * np.arange(b, dtype=np.uint64)
         batched_rsvd(m, n, A_ptrs, m, maxr, S_ptrs,
                      (U.data_ptr() + 8 * u_off.astype(np.uint64)) if want_vectors else None, m if want_vectors else None,
                      (V.data_ptr() + 8 * v_off.astype(np.uint64)) if want_vectors else None, n if want_vectors else None,
-                     eps=eps_a, rank=rank, err_est=err, info=info, seed=seed, flags=flags, ell0=ell0, device=dev)
-    return dict(S=S, U=U, V=V, u_off=u_off, v_off=v_off, rank=rank, err_est=err, info=info, max_rank=maxr)
+                     eps=eps_a, rank=rank, err_est=err, info=info, seed=seed, flags=flags, ell0=ell0, samples=samples,
+                     device=dev)
+    return dict(S=S, U=U, V=V, u_off=u_off, v_off=v_off, rank=rank, err_est=err, info=info, samples=samples,
+                max_rank=maxr)
+
+
+# ---- rank-prediction network -------------------------------------------------------------------
+
+def rank_features(buf, offs, m, n, seed=0):
+    """DEVICE float32 [b, 16] probe features of a packed batch (see pack_colmajor)."""
+    b = len(m)
+    out = torch.zeros((b, 16), dtype=torch.float32, device=buf.device)
+    if b:
+        ctx = _ctx(buf.device)
+        ptrs = buf.data_ptr() + buf.element_size() * np.asarray(offs).astype(np.uint64)
+        ctx.check(_lib.lib().bsvd_rank_features(ctx.h, b, _lib.as_ip(_lib.i32(m)), _lib.as_ip(_lib.i32(n)),
+                                                _lib.as_vp(_lib.ptrs(ptrs)), _lib.as_ip(_lib.i32(m)),
+                                                int(seed) & (2 ** 64 - 1), ctypes_ptr(out)))
+    return out
+
+
+class RankModel:
+    """The context's rank-prediction network (16-64-64-1 ReLU MLP, FP32) on a device."""
+
+    NPARAM = 5313
+
+    def __init__(self, device=None):
+        self.device = torch.device(device if device is not None else "cuda")
+        self.ctx = _ctx(self.device)
+
+    def init(self, seed=0):
+        self.ctx.check(_lib.lib().bsvd_rank_model_init(self.ctx.h, int(seed)))
+
+    def set(self, params, margin=4.0):
+        import ctypes
+        p = np.ascontiguousarray(np.asarray(params, dtype=np.float32))
+        assert p.size == self.NPARAM
+        self.ctx.check(_lib.lib().bsvd_rank_model_set(self.ctx.h, p.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                                      float(margin)))
+
+    def get(self):
+        import ctypes
+        p = np.zeros(self.NPARAM, dtype=np.float32)
+        mg = ctypes.c_float(0)
+        self.ctx.check(_lib.lib().bsvd_rank_model_get(self.ctx.h, p.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                                      ctypes.byref(mg)))
+        return p, mg.value
+
+    def save(self, path):
+        self.ctx.check(_lib.lib().bsvd_rank_model_save(self.ctx.h, str(path).encode()))
+
+    def load(self, path):
+        self.ctx.check(_lib.lib().bsvd_rank_model_load(self.ctx.h, str(path).encode()))
+
+    def forward(self, X):
+        X = X.to(device=self.device, dtype=torch.float32).contiguous()
+        y = torch.zeros(X.shape[0], dtype=torch.float32, device=self.device)
+        self.ctx.check(_lib.lib().bsvd_rank_model_forward(self.ctx.h, X.shape[0], ctypes_ptr(X), ctypes_ptr(y)))
+        return y
+
+    def loss_grad(self, X, T):
+        import ctypes
+        X = X.to(device=self.device, dtype=torch.float32).contiguous()
+        T = T.to(device=self.device, dtype=torch.float32).contiguous()
+        g = torch.zeros(self.NPARAM, dtype=torch.float32, device=self.device)
+        loss = ctypes.c_float(0)
+        self.ctx.check(_lib.lib().bsvd_rank_model_loss_grad(self.ctx.h, X.shape[0], ctypes_ptr(X), ctypes_ptr(T),
+                                                            ctypes.byref(loss), ctypes_ptr(g)))
+        return loss.value, g
+
+    def train(self, X, T, epochs=50, batch=256, lr=1e-3, seed=0):
+        import ctypes
+        X = X.to(device=self.device, dtype=torch.float32).contiguous()
+        T = T.to(device=self.device, dtype=torch.float32).contiguous()
+        loss = ctypes.c_float(0)
+        self.ctx.check(_lib.lib().bsvd_rank_model_train(self.ctx.h, X.shape[0], ctypes_ptr(X), ctypes_ptr(T),
+                                                        int(epochs), int(batch), float(lr), int(seed),
+                                                        ctypes.byref(loss)))
+        return loss.value

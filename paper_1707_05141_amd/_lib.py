@@ -24,8 +24,10 @@ SVD_NO_QR = 1 << 4
 SVD_JACOBI_ON_R = 1 << 5
 SVD_BLOCK_W8 = 1 << 6
 SVD_BLOCK_W32 = 1 << 7
+SVD_BLOCK_W16 = 1 << 8
 
 RSVD_FIXED = 1 << 0
+RSVD_LEARNED = 1 << 1
 
 _lib = None
 
@@ -58,18 +60,37 @@ def lib():
                               ctypes.c_double, ctypes.c_int, _vp, _vp, ctypes.c_uint]
     L.batched_qr.argtypes = [_vp, ctypes.c_int, ctypes.c_int, _ip, _ip, _vp, _ip, _vp, _ip, _vp, _ip]
     L.batched_rsvd.argtypes = [_vp, ctypes.c_int, _ip, _ip, _vp, _ip, _dp, _ip, _vp, _vp, _ip, _vp, _ip, _vp, _vp, _vp,
-                               ctypes.c_ulonglong, ctypes.c_uint, _ip]
+                               ctypes.c_ulonglong, ctypes.c_uint, _ip, _vp]
+    _fp = ctypes.POINTER(ctypes.c_float)
+    L.bsvd_rank_features.argtypes = [_vp, ctypes.c_int, _ip, _ip, _vp, _ip, ctypes.c_ulonglong, _vp]
+    L.bsvd_rank_model_nparam.restype = ctypes.c_int
+    L.bsvd_rank_model_init.argtypes = [_vp, ctypes.c_ulonglong]
+    L.bsvd_rank_model_set.argtypes = [_vp, _fp, ctypes.c_float]
+    L.bsvd_rank_model_get.argtypes = [_vp, _fp, _fp]
+    L.bsvd_rank_model_save.argtypes = [_vp, ctypes.c_char_p]
+    L.bsvd_rank_model_load.argtypes = [_vp, ctypes.c_char_p]
+    L.bsvd_rank_model_forward.argtypes = [_vp, ctypes.c_int, _vp, _vp]
+    L.bsvd_rank_model_loss_grad.argtypes = [_vp, ctypes.c_int, _vp, _vp, _fp, _vp]
+    L.bsvd_rank_model_train.argtypes = [_vp, ctypes.c_int, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_float,
+                                        ctypes.c_ulonglong, _fp]
     L.bsvd_sample_omega.argtypes = [_vp, ctypes.c_ulonglong, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                     _vp]
     L.bsvd_profile_enable.argtypes = [_vp, ctypes.c_int]
     L.bsvd_profile_read.argtypes = [_vp, ctypes.c_int, _dp, _dp, _dp, _ip]
+    L.bsvd_tune_get.argtypes = [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _ip,
+                                ctypes.POINTER(ctypes.c_float), _ip, ctypes.c_int]
+    L.bsvd_tune_save.argtypes = [_vp, ctypes.c_char_p]
+    L.bsvd_tune_load.argtypes = [_vp, ctypes.c_char_p]
     _lib = L
     return L
 
 
 def exported_symbols():
     return ["bsvd_create", "bsvd_destroy", "bsvd_last_error", "bsvd_sync", "bsvd_version", "batched_svd",
-            "batched_qr", "batched_rsvd", "bsvd_sample_omega", "bsvd_profile_enable", "bsvd_profile_read"]
+            "batched_qr", "batched_rsvd", "bsvd_sample_omega", "bsvd_profile_enable", "bsvd_profile_read",
+            "bsvd_tune_get", "bsvd_tune_save", "bsvd_tune_load", "bsvd_rank_features", "bsvd_rank_model_nparam",
+            "bsvd_rank_model_init", "bsvd_rank_model_set", "bsvd_rank_model_get", "bsvd_rank_model_save",
+            "bsvd_rank_model_load", "bsvd_rank_model_forward", "bsvd_rank_model_loss_grad", "bsvd_rank_model_train"]
 
 
 STAGES = ["rng", "sketch", "cgs", "qr", "project", "jacobi", "small", "output"]

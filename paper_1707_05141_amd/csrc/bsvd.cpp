@@ -5,6 +5,7 @@
 
 #include <cstdarg>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <map>
 #include <string>
@@ -123,9 +124,117 @@ void Ctx::prof_end(int idx, double bytes, double flops) {
     r.flops = flops;
 }
 
+// Time the candidate block widths on up to 128 instances of the class (writing into their own
+// outputs, which the full run then overwrites) and keep the fastest; cached per context. The sample
+// is large enough to fill the GPU with (matrix, block pair) tasks, so the timing reflects the
+// throughput regime of a large batch rather than the latency of a few matrices.
+int tune_block_width(Ctx *c, int dtype, int M, int N, const std::vector<int> &cls, const int *m, const int *n,
+                     const void *const *A, const int *lda, void *const *S, void *const *U, const int *ldu,
+                     void *const *V, const int *ldv, double tol, int max_sweeps, int *bw) {
+    const auto key = std::make_tuple(0, dtype, M, N);
+    auto it = c->tune.find(key);
+    if (it != c->tune.end()) {
+        *bw = it->second;
+        return BSVD_OK;
+    }
+    std::vector<int> sample(cls.begin(), cls.begin() + std::min<size_t>(cls.size(), 128));
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return c->fail(BSVD_EHIP, "hipEventCreate");
+    const bool prof = c->prof;
+    c->prof = false;
+    int best = 16;
+    float best_t = -1.0f;
+    std::vector<std::pair<int, float>> times;
+    for (int w : {8, 16, 32}) {
+        hipEventRecord(e0, c->stream);
+        int rc = block_jacobi_run(c, dtype, w, sample, m, n, A, lda, S, U, ldu, V, ldv, tol, max_sweeps, nullptr,
+                                  nullptr);
+        if (rc) {
+            c->prof = prof;
+            hipEventDestroy(e0);
+            hipEventDestroy(e1);
+            return rc;
+        }
+        hipEventRecord(e1, c->stream);
+        hipEventSynchronize(e1);
+        float ms = 0.0f;
+        hipEventElapsedTime(&ms, e0, e1);
+        times.push_back({w, ms});
+        if (best_t < 0.0f || ms < best_t) {
+            best_t = ms;
+            best = w;
+        }
+    }
+    c->prof = prof;
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    c->tune[key] = best;
+    c->tune_times[key] = times;
+    *bw = best;
+    return BSVD_OK;
+}
+
 }  // namespace bsvd
 
 extern "C" {
+
+int bsvd_tune_get(bsvd_ctx *ctx, int kind, int dtype, int M, int N, int *value, float *times_ms, int *candidates,
+                  int max_cand) {
+    if (!ctx || !value) return BSVD_EARG;
+    Ctx *c = reinterpret_cast<Ctx *>(ctx);
+    const auto key = std::make_tuple(kind, dtype, M, N);
+    auto it = c->tune.find(key);
+    if (it == c->tune.end()) return c->fail(BSVD_EARG, "no tuned entry for (%d, %d, %d, %d)", kind, dtype, M, N);
+    *value = it->second;
+    auto tt = c->tune_times.find(key);
+    int k = 0;
+    if (tt != c->tune_times.end())
+        for (auto &p : tt->second) {
+            if (k >= max_cand) break;
+            if (candidates) candidates[k] = p.first;
+            if (times_ms) times_ms[k] = p.second;
+            ++k;
+        }
+    for (; k < max_cand; ++k) {
+        if (candidates) candidates[k] = 0;
+        if (times_ms) times_ms[k] = 0.0f;
+    }
+    return BSVD_OK;
+}
+
+int bsvd_tune_save(const bsvd_ctx *ctx, const char *path) {
+    if (!ctx || !path) return BSVD_EARG;
+    const Ctx *c = reinterpret_cast<const Ctx *>(ctx);
+    FILE *f = fopen(path, "w");
+    if (!f) return BSVD_EARG;
+    fprintf(f, "# bsvd tune cache: kind dtype M N value\n");
+    for (auto &kv : c->tune)
+        fprintf(f, "%d %d %d %d %d\n", std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first),
+                std::get<3>(kv.first), kv.second);
+    fclose(f);
+    return BSVD_OK;
+}
+
+int bsvd_tune_load(bsvd_ctx *ctx, const char *path) {
+    if (!ctx || !path) return BSVD_EARG;
+    Ctx *c = reinterpret_cast<Ctx *>(ctx);
+    FILE *f = fopen(path, "r");
+    if (!f) return c->fail(BSVD_EARG, "cannot open %s", path);
+    char line[256];
+    int n = 0;
+    while (fgets(line, sizeof line, f)) {
+        if (line[0] == '#') continue;
+        int k, d, M, N, v;
+        if (sscanf(line, "%d %d %d %d %d", &k, &d, &M, &N, &v) == 5) {
+            if (k == 0 && v != 8 && v != 16 && v != 32) continue;  // only widths the kernels support
+            c->tune[std::make_tuple(k, d, M, N)] = v;
+            ++n;
+        }
+    }
+    fclose(f);
+    return BSVD_OK;
+}
 
 int bsvd_profile_enable(bsvd_ctx *ctx, int on) {
     if (!ctx) return BSVD_EARG;
@@ -191,6 +300,8 @@ void bsvd_destroy(bsvd_ctx *ctx) {
     if (c->dws) hipFree(c->dws);
     if (c->hws) hipHostFree(c->hws);
     if (c->rb) hipHostFree(c->rb);
+    if (c->model) hipFree(c->model);
+    if (c->mlp_scratch) hipFree(c->mlp_scratch);
     for (hipEvent_t ev : c->evpool) hipEventDestroy(ev);
     hipEventDestroy(c->staged);
     delete c;
@@ -276,12 +387,24 @@ int batched_svd(bsvd_ctx *ctx, int dtype, int batch, const int *m, const int *n,
             blk.push_back(b);
         }
     }
-    int bw = 16;
-    if (flags & BSVD_SVD_BLOCK_W8) bw = 8;
-    if (flags & BSVD_SVD_BLOCK_W32) bw = 32;
     if (!blk.empty()) {
-        int rc = block_jacobi_run(c, dtype, bw, blk, m, n, A, lda, S, U, ldu, V, ldv, tol, max_sweeps, sweeps, info);
-        if (rc) return rc;
+        // group by shape class; the block width is given by a flag or chosen by the autotuner
+        std::map<std::pair<int, int>, std::vector<int>> classes;
+        for (int b : blk) classes[{std::max(m[b], n[b]), std::min(m[b], n[b])}].push_back(b);
+        for (auto &kv : classes) {
+            int bw = 0;
+            if (flags & BSVD_SVD_BLOCK_W8) bw = 8;
+            if (flags & BSVD_SVD_BLOCK_W32) bw = 32;
+            if (flags & BSVD_SVD_BLOCK_W16) bw = 16;
+            if (!bw) {
+                int rc = tune_block_width(c, dtype, kv.first.first, kv.first.second, kv.second, m, n, A, lda, S, U, ldu,
+                                          V, ldv, tol, max_sweeps, &bw);
+                if (rc) return rc;
+            }
+            int rc = block_jacobi_run(c, dtype, bw, kv.second, m, n, A, lda, S, U, ldu, V, ldv, tol, max_sweeps, sweeps,
+                                      info);
+            if (rc) return rc;
+        }
     }
     if ((int)blk.size() == batch) return BSVD_OK;
 

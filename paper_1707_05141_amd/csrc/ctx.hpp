@@ -3,7 +3,9 @@
 
 #include <hip/hip_runtime.h>
 
+#include <map>
 #include <string>
+#include <tuple>
 #include <vector>
 
 namespace bsvd {
@@ -33,6 +35,20 @@ struct Ctx {
     void *rb = nullptr;
     size_t rb_size = 0;
     int ensure_readback(size_t bytes);
+
+    // Rank-prediction network: params | Adam m | Adam v | gradient | loss (floats), and scratch.
+    void *model = nullptr;
+    int adam_step = 0;
+    float rank_margin = 4.0f;
+    void *mlp_scratch = nullptr;
+    size_t mlp_scratch_size = 0;
+    int ensure_model();
+    int ensure_mlp_scratch(int n);
+
+    // Autotuner cache: (kind, dtype, M, N) -> chosen parameter, with the measured times per
+    // candidate (kind 0 = block-Jacobi width).
+    std::map<std::tuple<int, int, int, int>, int> tune;
+    std::map<std::tuple<int, int, int, int>, std::vector<std::pair<int, float>>> tune_times;
 
     // Per-stage profiling: HIP events recorded on `stream` around launch groups (off by default).
     struct ProfRec {

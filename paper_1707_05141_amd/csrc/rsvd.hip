@@ -18,6 +18,7 @@
 
 #include "common.hpp"
 #include "rsvd.hpp"
+#include "mlp.hpp"
 
 namespace bsvd {
 
@@ -274,7 +275,7 @@ __global__ void check_kernel(RsvdState *__restrict__ st, const int *__restrict__
 // the outputs S[:k], rank, error estimate and info.
 __global__ void finalize_kernel(RsvdState *__restrict__ st, const int *__restrict__ list, int count,
                                 int *__restrict__ rank_out, double *__restrict__ err_out, int *__restrict__ info_out,
-                                const int *__restrict__ jinfo, int *__restrict__ rank_copy) {
+                                const int *__restrict__ jinfo, int *__restrict__ rank_copy, int *__restrict__ ell_out) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= count) return;
     const int inst = list[t];
@@ -317,14 +318,32 @@ __global__ void finalize_kernel(RsvdState *__restrict__ st, const int *__restric
     S.rank = S.nonfinite ? 0 : kk;
     for (int i = 0; i < kk && !S.nonfinite; ++i) S.Sout[i] = sg[i];
     if (rank_out) rank_out[inst] = S.rank;
+    if (ell_out) ell_out[inst] = ell;
     rank_copy[t] = S.rank;
     if (err_out) err_out[inst] = normA2 > 0.0 ? sqrt(terr / normA2) : 0.0;
     if (info_out) info_out[inst] = info;
 }
 
+// Initial sample count from the network's prediction y (rank / 16): ell0 = ceil(16 y + margin),
+// clamped to [1, cap].
+__global__ void ell0_kernel(const float *__restrict__ y, const int *__restrict__ cap, int count, float margin,
+                            int *__restrict__ ell0) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= count) return;
+    float v = ceilf(16.0f * y[t] + margin);
+    int e = __builtin_isfinite(v) ? (int)fminf(fmaxf(v, 1.0f), (float)cap[t]) : cap[t];
+    ell0[t] = e;
+}
+
 // ---------------------------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------------------------
+hipError_t launch_ell0(const float *y, const int *cap, int count, float margin, int *ell0, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(ell0_kernel, dim3((count + 255) / 256), dim3(256), 0, st, y, cap, count, margin, ell0);
+    return hipGetLastError();
+}
+
 hipError_t launch_rng(const RngDesc *d, const int2 *tiles, int ntiles, unsigned long long seed, hipStream_t st) {
     if (ntiles <= 0) return hipSuccess;
     hipLaunchKernelGGL(rng_kernel, dim3(ntiles), dim3(256), 0, st, d, tiles, seed);
@@ -376,10 +395,10 @@ hipError_t launch_check(RsvdState *st, const int *list, int count, int *flags, h
 }
 
 hipError_t launch_finalize(RsvdState *st, const int *list, int count, int *rank, double *err, int *info,
-                           const int *jinfo, int *rank_copy, hipStream_t s) {
+                           const int *jinfo, int *rank_copy, int *ell_out, hipStream_t s) {
     if (count <= 0) return hipSuccess;
     hipLaunchKernelGGL(finalize_kernel, dim3(nblk(count, 256)), dim3(256), 0, s, st, list, count, rank, err, info,
-                       jinfo, rank_copy);
+                       jinfo, rank_copy, ell_out);
     return hipGetLastError();
 }
 

@@ -46,6 +46,7 @@ hipError_t launch_grow_decide(RsvdState *st, const GrowItem *items, int count, i
 hipError_t launch_init_norm(RsvdState *st, const GrowItem *items, int count, hipStream_t s);
 hipError_t launch_check(RsvdState *st, const int *list, int count, int *flags, hipStream_t s);
 hipError_t launch_finalize(RsvdState *st, const int *list, int count, int *rank, double *err, int *info,
-                           const int *jinfo, int *rank_copy, hipStream_t s);
+                           const int *jinfo, int *rank_copy, int *ell_out, hipStream_t s);
+hipError_t launch_ell0(const float *y, const int *cap, int count, float margin, int *ell0, hipStream_t st);
 
 }  // namespace bsvd

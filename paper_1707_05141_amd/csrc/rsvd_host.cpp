@@ -28,6 +28,7 @@
 #include "ctx.hpp"
 #include "plan.hpp"
 #include "rsvd.hpp"
+#include "mlp.hpp"
 
 using namespace bsvd;
 
@@ -76,10 +77,147 @@ struct MMGroup {
 
 }  // namespace
 
+// Probe features of every instance: Y = A Omega_p (PROBE_COLS Gaussian columns at counter column
+// PROBE_COL0), R = qr(Y), features from diag(R). Omp (n x kp row-major), Y (m x kp) and R (kp x kp,
+// ld ldr) are per-instance scratch given as device pointers. Enqueued on the context's stream.
+struct ProbeBufs {
+    double *Om, *Y, *R;
+    int ldr;
+};
+
+static int probe_features(Ctx *c, int batch, const int *m, const int *n, const void *const *A, const int *lda,
+                          const std::vector<ProbeBufs> &pb, unsigned long long seed, float *feats, size_t desc_cap) {
+    Packer p;
+    int rc = c->ensure_host(desc_cap);
+    if (rc) return rc;
+    p.h = static_cast<char *>(c->hws);
+    p.d = static_cast<char *>(c->dws);
+    p.cap = desc_cap;
+    RngDesc *drd;
+    RngDesc *hrd = p.put<RngDesc>(batch, &drd);
+    FeatDesc *dfd;
+    FeatDesc *hfd = p.put<FeatDesc>(batch, &dfd);
+    if (!hrd || !hfd) return c->fail(BSVD_EHIP, "internal: descriptor region overflow");
+    std::vector<int2> rt;
+    std::map<int, MMGroup> sk;
+    std::vector<QrDesc> qv;
+    std::map<QKey, std::vector<int>> qbins;
+    double skb = 0, skf = 0;
+    for (int b = 0; b < batch; ++b) {
+        const int kp = std::min(PROBE_COLS, std::min(m[b], n[b]));
+        hrd[b] = RngDesc{pb[b].Om, n[b], kp, PROBE_COL0, kp, b};
+        for (int t = 0; t < cdiv(n[b] * kp, 256); ++t) rt.push_back(make_int2(b, t));
+        MMDesc d;
+        d.X = static_cast<const double *>(A[b]); d.Y = pb[b].Om; d.C = pb[b].Y; d.xsq = nullptr; d.csq = nullptr;
+        d.alpha = 1.0; d.beta = 0.0; d.M = m[b]; d.N = kp; d.K = n[b]; d.ldx = lda[b]; d.ldy = kp; d.ldc = m[b];
+        d.ytrans = 1;
+        sk[nmax_for(kp)].desc.push_back(d);
+        sk[nmax_for(kp)].tiles_per.push_back(cdiv(m[b], 64));
+        QrDesc q;
+        q.A = pb[b].Y; q.m = m[b]; q.n = kp; q.lda = m[b]; q.trans = 0; q.Q = nullptr; q.ldq = 0; q.R = pb[b].R;
+        q.ldr = pb[b].ldr;
+        qv.push_back(q);
+        QKey k;
+        if (!qr_config(m[b], kp, &k.nb, &k.seg, &k.kr)) return c->fail(BSVD_EUNSUP, "instance %d: probe QR", b);
+        qbins[k].push_back(b);
+        hfd[b] = FeatDesc{pb[b].R, pb[b].ldr, kp, m[b], n[b], b};
+        skb += 8.0 * ((double)m[b] * n[b] + (double)(m[b] + n[b]) * kp);
+        skf += 2.0 * (double)m[b] * n[b] * kp;
+    }
+    int2 *drt;
+    int2 *hrt = p.put<int2>(rt.size(), &drt);
+    if (hrt) std::copy(rt.begin(), rt.end(), hrt);
+    QrDesc *dq;
+    QrDesc *hq = p.put<QrDesc>(qv.size(), &dq);
+    if (hq) std::copy(qv.begin(), qv.end(), hq);
+    std::vector<std::pair<QKey, std::pair<const int *, int>>> ql;
+    for (auto &kv : qbins) {
+        int *dl;
+        int *hl = p.put<int>(kv.second.size(), &dl);
+        if (!hl) break;
+        std::copy(kv.second.begin(), kv.second.end(), hl);
+        ql.push_back({kv.first, {dl, (int)kv.second.size()}});
+    }
+    std::vector<std::pair<MMDesc *, std::pair<int2 *, int>>> mm;
+    std::vector<int> mmn;
+    for (auto &kv : sk) {
+        MMDesc *dd;
+        MMDesc *hd = p.put<MMDesc>(kv.second.desc.size(), &dd);
+        int nt = 0;
+        for (int t : kv.second.tiles_per) nt += t;
+        int2 *dt;
+        int2 *ht = p.put<int2>(nt, &dt);
+        if (!hd || !ht) break;
+        int k = 0;
+        for (size_t i = 0; i < kv.second.desc.size(); ++i) {
+            hd[i] = kv.second.desc[i];
+            for (int t = 0; t < kv.second.tiles_per[i]; ++t) ht[k++] = make_int2((int)i, t);
+        }
+        mm.push_back({dd, {dt, nt}});
+        mmn.push_back(kv.first);
+    }
+    if (p.overflow) return c->fail(BSVD_EHIP, "internal: descriptor region overflow");
+    if ((rc = c->upload_to(0, p.off))) return rc;
+    int pi = c->prof_begin(BSVD_STAGE_RNG);
+    hipError_t e = launch_rng(drd, drt, (int)rt.size(), seed, c->stream);
+    if (e != hipSuccess) return c->hip_fail(e, "rng launch");
+    c->prof_end(pi, 0.0, 0.0);
+    pi = c->prof_begin(BSVD_STAGE_SKETCH);
+    for (size_t i = 0; i < mm.size(); ++i) {
+        e = launch_gemm_nn(mmn[i], mm[i].first, mm[i].second.first, mm[i].second.second, c->stream);
+        if (e != hipSuccess) return c->hip_fail(e, "probe sketch launch");
+    }
+    c->prof_end(pi, skb, skf);
+    pi = c->prof_begin(BSVD_STAGE_QR);
+    for (auto &L : ql) {
+        e = launch_qr(0, L.first.nb, L.first.seg, L.first.kr, dq, L.second.first, L.second.second, c->stream);
+        if (e != hipSuccess) return c->hip_fail(e, "probe qr launch");
+    }
+    c->prof_end(pi, 0.0, 0.0);
+    pi = c->prof_begin(BSVD_STAGE_SMALL);
+    e = launch_features(dfd, batch, feats, c->stream);
+    if (e != hipSuccess) return c->hip_fail(e, "features launch");
+    c->prof_end(pi, 0.0, 0.0);
+    return BSVD_OK;
+}
+
+extern "C" int bsvd_rank_features(bsvd_ctx *ctx, int batch, const int *m, const int *n, const void *const *A,
+                                  const int *lda, unsigned long long seed, float *feats) {
+    if (!ctx) return BSVD_EARG;
+    Ctx *c = reinterpret_cast<Ctx *>(ctx);
+    c->err.clear();
+    if (batch < 0) return c->fail(BSVD_EARG, "batch = %d < 0", batch);
+    if (batch == 0) return BSVD_OK;
+    if (!m || !n || !A || !lda || !feats) return c->fail(BSVD_EARG, "m, n, A, lda and feats must be non-NULL");
+    size_t dsz = 1u << 16;
+    for (int b = 0; b < batch; ++b) {
+        if (m[b] < 1 || n[b] < 1 || m[b] > 512 || n[b] > 512 || lda[b] < m[b] || !A[b])
+            return c->fail(BSVD_EARG, "instance %d: bad shape / lda / pointer", b);
+        dsz += 1024 + 8 * (size_t)cdiv(n[b] * PROBE_COLS, 256) + 16 * (size_t)cdiv(m[b], 64);
+    }
+    dsz = (dsz + 4095) & ~(size_t)4095;
+    Arena ar;
+    ar.off = dsz;
+    std::vector<ProbeBufs> pb(batch);
+    std::vector<size_t> o(3 * (size_t)batch);
+    for (int b = 0; b < batch; ++b) {
+        o[3 * b] = ar.alloc(8 * (size_t)n[b] * PROBE_COLS);
+        o[3 * b + 1] = ar.alloc(8 * (size_t)m[b] * PROBE_COLS);
+        o[3 * b + 2] = ar.alloc(8 * (size_t)PROBE_COLS * PROBE_COLS);
+    }
+    int rc = c->ensure_device(ar.off);
+    if (rc) return rc;
+    char *db = static_cast<char *>(c->dws);
+    for (int b = 0; b < batch; ++b)
+        pb[b] = ProbeBufs{reinterpret_cast<double *>(db + o[3 * b]), reinterpret_cast<double *>(db + o[3 * b + 1]),
+                          reinterpret_cast<double *>(db + o[3 * b + 2]), PROBE_COLS};
+    return probe_features(c, batch, m, n, A, lda, pb, seed, feats, dsz);
+}
+
 extern "C" int batched_rsvd(bsvd_ctx *ctx, int batch, const int *m, const int *n, const void *const *A,
                             const int *lda, const double *eps, const int *max_rank, void *const *S, void *const *U,
                             const int *ldu, void *const *V, const int *ldv, int *rank, double *err_est, int *info,
-                            unsigned long long seed, unsigned flags, const int *ell0) {
+                            unsigned long long seed, unsigned flags, const int *ell0, int *samples) {
     if (!ctx) return BSVD_EARG;
     Ctx *c = reinterpret_cast<Ctx *>(ctx);
     c->err.clear();
@@ -89,7 +227,12 @@ extern "C" int batched_rsvd(bsvd_ctx *ctx, int batch, const int *m, const int *n
     if (U && !ldu) return c->fail(BSVD_EARG, "U given without ldu");
     if (V && !ldv) return c->fail(BSVD_EARG, "V given without ldv");
     if ((flags & BSVD_RSVD_FIXED) && !ell0) return c->fail(BSVD_EARG, "BSVD_RSVD_FIXED needs ell0");
-    if (flags & ~(unsigned)(BSVD_RSVD_FIXED)) return c->fail(BSVD_EUNSUP, "flags 0x%x not supported", flags);
+    if ((flags & BSVD_RSVD_LEARNED) && (ell0 || (flags & BSVD_RSVD_FIXED)))
+        return c->fail(BSVD_EARG, "BSVD_RSVD_LEARNED chooses ell0 itself (pass ell0 = NULL, no FIXED)");
+    if ((flags & BSVD_RSVD_LEARNED) && !c->model) return c->fail(BSVD_EARG, "BSVD_RSVD_LEARNED needs a rank model");
+    if (flags & ~(unsigned)(BSVD_RSVD_FIXED | BSVD_RSVD_LEARNED))
+        return c->fail(BSVD_EUNSUP, "flags 0x%x not supported", flags);
+    const bool learned = (flags & BSVD_RSVD_LEARNED) != 0;
     hipError_t e = hipSetDevice(c->device);
     if (e != hipSuccess) return c->hip_fail(e, "hipSetDevice");
 
@@ -118,7 +261,8 @@ extern "C" int batched_rsvd(bsvd_ctx *ctx, int batch, const int *m, const int *n
         q.ell0 = ell0 ? std::min(std::max(ell0[b], 0), q.cap) : 0;
         if ((flags & BSVD_RSVD_FIXED) && q.ell0 < 1) return c->fail(BSVD_EARG, "instance %d: ell0 < 1 with FIXED", b);
         q.maxr = max_rank[b];
-        const int bmax = std::max(GROW_BLK, q.ell0);
+        if (learned) q.ell0 = q.cap;  // the learned count is at most cap: size buffers for it
+        const int bmax = std::max(std::max(GROW_BLK, q.ell0), PROBE_COLS);
         dsz += 4096 + 8 * (size_t)cdiv(q.n * bmax, 256) + 96 * (size_t)cdiv(q.m, 64) + 96 * (size_t)cdiv(q.n, 64);
     }
     dsz = (dsz + 4095) & ~(size_t)4095;
@@ -128,10 +272,13 @@ extern "C" int batched_rsvd(bsvd_ctx *ctx, int batch, const int *m, const int *n
     const size_t oJinfo = ar.alloc(sizeof(int) * (size_t)batch);
     const size_t oFlags = ar.alloc(sizeof(int) * (size_t)batch);
     const size_t oRankc = ar.alloc(sizeof(int) * (size_t)batch);
+    const size_t oFeat = ar.alloc(sizeof(float) * MLP_IN * (size_t)batch);
+    const size_t oPred = ar.alloc(sizeof(float) * (size_t)batch);
+    const size_t oCap = ar.alloc(sizeof(int) * (size_t)batch);
     for (int b = 0; b < batch; ++b) {
         Inst &q = I[b];
         const size_t M = q.m, N = q.n, C = q.cap;
-        const size_t bmax = std::max(GROW_BLK, q.ell0);
+        const size_t bmax = std::max(std::max(GROW_BLK, q.ell0), PROBE_COLS);
         q.oQ = ar.alloc(8 * M * C);
         q.oY = ar.alloc(8 * M * C);
         q.oOm = ar.alloc(8 * N * bmax);
@@ -278,6 +425,28 @@ extern "C" int batched_rsvd(bsvd_ctx *ctx, int batch, const int *m, const int *n
         }
         return BSVD_OK;
     };
+
+    // ---- learned initial sample count: probe features -> network -> ell0 ----------------------
+    if (learned) {
+        std::vector<ProbeBufs> pb(batch);
+        for (int b = 0; b < batch; ++b) pb[b] = ProbeBufs{dptr(I[b].oOm), dptr(I[b].oY), dptr(I[b].oRB), I[b].cap};
+        float *dfeat = reinterpret_cast<float *>(db + oFeat);
+        float *dpred = reinterpret_cast<float *>(db + oPred);
+        int *dcap = reinterpret_cast<int *>(db + oCap);
+        if ((rc = probe_features(c, batch, m, n, A, lda, pb, seed, dfeat, dsz))) return rc;
+        if ((rc = c->ensure_host(dsz))) return rc;
+        int *hc = static_cast<int *>(c->hws);
+        for (int b = 0; b < batch; ++b) hc[b] = I[b].cap;
+        if ((rc = c->upload_to(oCap, sizeof(int) * (size_t)batch))) return rc;
+        int pi = c->prof_begin(BSVD_STAGE_SMALL);
+        e = launch_mlp_forward(static_cast<const float *>(c->model), batch, dfeat, dpred, c->stream);
+        if (e != hipSuccess) return c->hip_fail(e, "mlp forward launch");
+        e = launch_ell0(dpred, dcap, batch, c->rank_margin, dflags, c->stream);
+        if (e != hipSuccess) return c->hip_fail(e, "ell0 launch");
+        c->prof_end(pi, 0.0, 0.0);
+        if ((rc = readback(batch))) return rc;
+        for (int b = 0; b < batch; ++b) I[b].ell0 = rb[b];
+    }
 
     // ---- phase A: initial block of ell0 samples (Algorithm 4 as printed) -------------------
     std::vector<int> grow, pend_check, finished;
@@ -547,7 +716,7 @@ extern "C" int batched_rsvd(bsvd_ctx *ctx, int batch, const int *m, const int *n
         }
         c->prof_end(pi, jb_, 0.0);
         pi = c->prof_begin(BSVD_STAGE_SMALL);
-        e = launch_finalize(dstate, dl, F, rank, err_est, info, djinfo, drankc, c->stream);
+        e = launch_finalize(dstate, dl, F, rank, err_est, info, djinfo, drankc, samples, c->stream);
         if (e != hipSuccess) return c->hip_fail(e, "finalize launch");
         c->prof_end(pi, 0.0, 0.0);
         e = hipMemcpyAsync(c->rb, drankc, sizeof(int) * (size_t)F, hipMemcpyDeviceToHost, c->stream);

@@ -12,7 +12,7 @@ pytestmark = pytest.mark.gpu
 import paper_1707_05141_amd as P  # noqa: E402
 from paper_1707_05141_amd import _lib  # noqa: E402
 
-W_FLAGS = {8: _lib.SVD_BLOCK_W8, 16: 0, 32: _lib.SVD_BLOCK_W32}
+W_FLAGS = {8: _lib.SVD_BLOCK_W8, 16: _lib.SVD_BLOCK_W16, 32: _lib.SVD_BLOCK_W32}
 
 
 def _svd(A_np, flags, dtype=torch.float64):
@@ -71,3 +71,17 @@ def test_block_auto_route_large():
     for b in range(2):
         assert info[b] == 0
         check_svd(A[b], S[b], U[b], V[b], So[b], Uo[b], Vo[b], 1e-12, vec_tol=1e-8, fac_tol=1e-12)
+
+
+def test_block_autotuner_picks_and_persists(tmp_path):
+    A = synth.batch_gaussian(4, 96, 64, seed=12)
+    S, U, V, sw, info = _svd(A, _lib.SVD_FORCE_BLOCK)
+    assert np.all(info == 0)
+    tuned = P.tune_get(0, 0, 96, 64)
+    assert tuned is not None and tuned[0] in (8, 16, 32) and set(tuned[1]) == {8, 16, 32}
+    So = oracle.batched_jacobi_svd(A, want_vectors=False)[0]
+    np.testing.assert_allclose(S, So, rtol=0, atol=1e-12 * So.max())
+    p = tmp_path / "tune.txt"
+    P.tune_save(p)
+    assert "0 0 96 64 %d" % tuned[0] in p.read_text()
+    P.tune_load(p)

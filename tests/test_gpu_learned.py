@@ -1,0 +1,112 @@
+"""GPU tests of the learned part: probe features, the rank network's HIP forward / backward / Adam
+kernels against the FP64 CPU oracle, and what the trained network gains inside batched_rsvd."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1707_05141_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+import paper_1707_05141_amd as P  # noqa: E402
+from paper_1707_05141_amd import _lib, rankmodel  # noqa: E402
+
+EPS = 1e-6
+
+
+def test_features_match_oracle():
+    shapes = [(64, 64), (128, 512), (512, 64), (10, 40), (40, 7), (256, 256)]
+    mats = [synth.kernel_block(m, n, 8, i, "exp" if i % 2 else "inv") for i, (m, n) in enumerate(shapes)]
+    mats.append(np.zeros((64, 128)))
+    buf, offs, m, n = P.pack_colmajor(mats)
+    f = P.rank_features(buf, offs, m, n, seed=31).cpu().numpy()
+    for b, A in enumerate(mats):
+        fo = oracle.features(A, seed=31, inst=b)
+        np.testing.assert_allclose(f[b], fo, rtol=0, atol=2e-6)
+
+
+def _rand_params(rng):
+    p = rng.standard_normal(5313).astype(np.float32) * 0.2
+    return p
+
+
+def test_forward_and_gradient_match_oracle():
+    rng = np.random.default_rng(0)
+    M = P.RankModel()
+    p = _rand_params(rng)
+    M.set(p, margin=3.0)
+    p_back, mg = M.get()
+    np.testing.assert_array_equal(p_back, p)
+    assert mg == 3.0
+    X = rng.standard_normal((300, 16)).astype(np.float32)
+    T = rng.standard_normal(300).astype(np.float32)
+    y = M.forward(torch.from_numpy(X)).cpu().numpy()
+    yo = oracle.mlp_forward(p.astype(np.float64), X.astype(np.float64))
+    np.testing.assert_allclose(y, yo, rtol=1e-5, atol=1e-5)
+    loss, g = M.loss_grad(torch.from_numpy(X), torch.from_numpy(T))
+    lo, go = oracle.mlp_loss_grad(p.astype(np.float64), X.astype(np.float64), T.astype(np.float64))
+    assert abs(loss - lo) <= 1e-5 * abs(lo)
+    g = g.cpu().numpy()
+    # FP32 gradients vs the FP64 reference, relative to the largest gradient entry
+    assert np.max(np.abs(g - go)) <= 1e-4 * np.max(np.abs(go))
+
+
+def test_training_is_deterministic_and_reduces_loss():
+    rng = np.random.default_rng(1)
+    X = rng.standard_normal((2048, 16)).astype(np.float32)
+    w = rng.standard_normal(16).astype(np.float32)
+    T = (np.maximum(X @ w, 0) / 4).astype(np.float32)
+    M = P.RankModel()
+    M.init(seed=5)
+    l0, _ = M.loss_grad(torch.from_numpy(X), torch.from_numpy(T))
+    l1 = M.train(torch.from_numpy(X), torch.from_numpy(T), epochs=20, batch=128, lr=2e-3, seed=7)
+    p1, _ = M.get()
+    M.init(seed=5)
+    l2 = M.train(torch.from_numpy(X), torch.from_numpy(T), epochs=20, batch=128, lr=2e-3, seed=7)
+    p2, _ = M.get()
+    np.testing.assert_array_equal(p1, p2)
+    assert l1 == l2
+    assert l1 < 0.1 * l0
+
+
+def test_learned_rsvd_gain_on_held_out_blocks():
+    """Train on generated kernel blocks (labels: ranks from the FP64 method), then compare the learned
+    sample count with the plain adaptive finder on held-out blocks: same accuracy and ranks, fewer
+    passes over A."""
+    rng = np.random.default_rng(2)
+    sizes = [64, 128, 256]
+    tr_shapes = [(int(rng.choice(sizes)), int(rng.choice(sizes))) for _ in range(600)]
+    te_shapes = [(int(rng.choice(sizes)), int(rng.choice(sizes))) for _ in range(120)]
+    kinds = ["exp", "inv"]
+    tr = [synth.kernel_block(m, n, 101, i, kinds[i % 2]) for i, (m, n) in enumerate(tr_shapes)]
+    te = [synth.kernel_block(m, n, 202, i, kinds[i % 2]) for i, (m, n) in enumerate(te_shapes)]
+    model = rankmodel.train_from_blocks(tr, eps=EPS, seed=3, epochs=150)
+    buf, offs, m, n = P.pack_colmajor(te)
+    P.profile_enable(True)
+    plain = P.rsvd_packed(buf, offs, m, n, eps=EPS, seed=9)
+    torch.cuda.synchronize()
+    prof_plain = P.profile_read()
+    learned = P.rsvd_packed(buf, offs, m, n, eps=EPS, seed=9, flags=_lib.RSVD_LEARNED)
+    torch.cuda.synchronize()
+    prof_learned = P.profile_read()
+    P.profile_enable(False)
+    a_bytes = float(sum(8.0 * A.size for A in te))
+    passes = lambda pr: (pr["sketch"]["bytes"] + pr["project"]["bytes"]) / a_bytes
+    for res in (plain, learned):
+        assert np.all(res["info"].cpu().numpy() == 0)
+        assert res["err_est"].max().item() <= EPS
+    rk_p = plain["rank"].cpu().numpy()
+    rk_l = learned["rank"].cpu().numpy()
+    assert np.sum(rk_p != rk_l) <= 1  # near-ties only
+    for b in range(0, len(te), 7):
+        k = int(rk_l[b])
+        mm, nn = te[b].shape
+        S = learned["S"][b, :k].cpu().numpy()
+        U = learned["U"][int(learned["u_off"][b]):int(learned["u_off"][b]) + mm * k].cpu().numpy().reshape(k, mm).T
+        V = learned["V"][int(learned["v_off"][b]):int(learned["v_off"][b]) + nn * k].cpu().numpy().reshape(k, nn).T
+        assert np.linalg.norm(te[b] - (U * S) @ V.T) <= EPS * np.linalg.norm(te[b])
+    print("passes over A: plain %.2f, learned %.2f; mean samples plain %.1f learned %.1f"
+          % (passes(prof_plain), passes(prof_learned), plain["samples"].float().mean().item(),
+             learned["samples"].float().mean().item()))
+    assert passes(prof_learned) < passes(prof_plain) - 1.0
