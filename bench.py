@@ -348,7 +348,125 @@ def run_c3(args, torch, P, synth):
     return res
 
 
-WORKLOADS = {"c1": run_c1, "c2": run_c2, "c3": run_c3, "c4": run_c4}
+def run_c5(args, torch, P, synth):
+    """100,000 blocks mixing exp(-|x-y|/0.1) blocks, 1/|x-y| blocks (both on the two-squares geometry)
+    and U diag(exp(-(i/w)^2)) V^T blocks (Haar U, V, w ~ U[4, 64]) in equal thirds; m, n uniform on
+    {64, 128, 256, 512}; randomized SVD to relative Frobenius error 1e-6. The rank network is trained
+    first (outside the timed region) on 6,000 blocks of the same mixture drawn with another seed; then
+    the learned sample count (value) and the plain adaptive finder are timed on the same batch."""
+    import oracle
+    from paper_1707_05141_amd import _lib, rankmodel
+    count = args.c5_count
+    eps, max_rank, oseed = 1e-6, 64, 777
+    # ---- training set and model (untimed)
+    t0 = time.perf_counter()
+    tm, tn, tk, tw = synth.c5_mixture(6000, seed=501)
+    tbuf, toffs = synth.mixed_blocks_packed(tm, tn, tk, tw, seed=501)
+    model = rankmodel.train_packed(tbuf, toffs, tm, tn, eps=eps, seed=11, epochs=60)
+    del tbuf
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    # ---- benchmark batch
+    t0 = time.perf_counter()
+    m, n, kinds, w = synth.c5_mixture(count, seed=5)
+    buf, offs = synth.mixed_blocks_packed(m, n, kinds, w, seed=5)
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - t0
+    o = _rsvd_buffers(torch, m, n, max_rank)
+    samples = torch.zeros(count, dtype=torch.int32, device="cuda")
+    A_ptrs = buf.data_ptr() + 8 * offs.astype(np.uint64)
+    S_ptrs = o["S"].data_ptr() + 8 * max_rank * np.arange(count, dtype=np.uint64)
+    U_ptrs = o["U"].data_ptr() + 8 * o["u_off"].astype(np.uint64)
+    V_ptrs = o["V"].data_ptr() + 8 * o["v_off"].astype(np.uint64)
+    eps_a = np.full(count, eps)
+    a_bytes = float((8 * m.astype(np.float64) * n).sum())
+
+    def run(flags, steps, warmup):
+        def step():
+            P.batched_rsvd(m, n, A_ptrs, m, o["maxr"], S_ptrs, U_ptrs, m, V_ptrs, n, eps=eps_a, rank=o["rank"],
+                           err_est=o["err"], info=o["info"], seed=oseed, flags=flags, samples=samples)
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        P.profile_enable(True)
+        t1 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t1) / steps
+        prof = P.profile_read()
+        P.profile_enable(False)
+        info = o["info"].cpu().numpy()
+        rank = o["rank"].cpu().numpy()
+        err = o["err"].cpu().numpy()
+        return dict(ms=wall * 1e3, prof=prof, info=info, rank=rank, err=err, samples=samples.cpu().numpy().copy())
+
+    half = max(1, args.steps // 2)
+    variants = {"plain_fp64": (0, half), "mixed": (_lib.RSVD_MIXED, half), "learned_fp64": (_lib.RSVD_LEARNED, half),
+                "learned_mixed": (_lib.RSVD_LEARNED | _lib.RSVD_MIXED, args.steps)}
+    runs = {name: run(fl, st, 1 if name != "learned_mixed" else args.warmup) for name, (fl, st) in variants.items()}
+    plain, learned = runs["plain_fp64"], runs["learned_mixed"]
+    ok = (learned["info"] == 0)
+    capped = learned["info"] == 2
+    assert np.all((learned["info"] == 0) | capped), np.bincount(learned["info"])
+    assert learned["err"][ok].max() <= eps
+    mism = int(np.sum((learned["rank"] != plain["rank"]) & ok & (plain["info"] == 0)))
+    # parity spot check: the result is checked by definition against the oracle (error <= eps and rank
+    # = the oracle's exact truncation rank from its full Jacobi SVD, for blocks the oracle finishes fast)
+    rng = np.random.default_rng(2)
+    idx = rng.choice(np.nonzero(ok)[0], 12, replace=False)
+    nbad = 0
+    for i in idx:
+        mi, ni = int(m[i]), int(n[i])
+        A = buf[int(offs[i]):int(offs[i]) + mi * ni].cpu().numpy().reshape(ni, mi).T
+        k = int(learned["rank"][i])
+        Ug = o["U"][int(o["u_off"][i]):int(o["u_off"][i]) + mi * k].cpu().numpy().reshape(k, mi).T
+        Vg = o["V"][int(o["v_off"][i]):int(o["v_off"][i]) + ni * k].cpu().numpy().reshape(k, ni).T
+        Sg = o["S"][i, :k].cpu().numpy()
+        rel = np.linalg.norm(A - (Ug * Sg) @ Vg.T) / np.linalg.norm(A)
+        assert rel <= eps, (i, rel)
+        if min(mi, ni) <= 128:
+            S_full = oracle.jacobi_svd(A)[0]
+            nbad += int(k != oracle.rank_rule(S_full, float((A ** 2).sum()), eps)[0])
+
+    def passes(r, steps):
+        return (r["prof"]["sketch"]["bytes"] + r["prof"]["project"]["bytes"]) / steps / a_bytes
+
+    lp = learned["prof"]
+    dom = max(("sketch", "project", "cgs", "qr", "jacobi", "output"), key=lambda s: lp[s]["ms"])
+    dom_ms = lp[dom]["ms"] / max(1, lp[dom]["launches"])
+    dom_bytes = lp[dom]["bytes"] / max(1, lp[dom]["launches"])
+    bound = "hbm" if dom in ("sketch", "project") else "alu"
+    if bound == "hbm":
+        roof = dict(bound="hbm", achieved=dom_bytes / (dom_ms * 1e-3) / 1e9, peak=HBM_PEAK_GBS, unit="GB/s")
+    else:
+        fl = lp[dom]["flops"] / max(1, lp[dom]["launches"])
+        roof = dict(bound="alu", achieved=fl / (dom_ms * 1e-3) / 1e12, peak=FP64_PEAK_TFLOPS, unit="TFLOP/s")
+    roof.update(frac=roof["achieved"] / roof["peak"], traffic=None, kernel="stage:" + dom, kernel_ms=dom_ms,
+                bytes_per_launch=dom_bytes)
+    per_variant = {name: dict(ms=r["ms"], svds_per_s=count / (r["ms"] * 1e-3),
+                              passes_over_A=passes(r, variants[name][1]), mean_samples=float(r["samples"].mean()),
+                              max_err_est_ok=float(r["err"][r["info"] == 0].max()),
+                              info2_fraction=float(np.mean(r["info"] == 2)))
+                   for name, r in runs.items()}
+    kinds_a = np.asarray(kinds)
+    res = dict(value=count / (learned["ms"] * 1e-3), unit="SVDs/s", ms_per_step=learned["ms"], dtype="f32+f64",
+               config=dict(workload="rsvd_mixed_learned_100000_blocks_exp_inv_gaussdecay", batch=count, eps=eps,
+                           max_rank=max_rank, basis_cap=64,
+                           precision="learned initial sample count + FP32 sketch products; FP64 basis QR, "
+                                     "projection, check, rank rule and small SVD",
+                           variants=per_variant, speedup_mixed_learned_vs_plain_fp64=plain["ms"] / learned["ms"],
+                           info2_rank_above_cap_fraction=float(capped.mean()),
+                           info2_by_kind={k: float(np.mean(capped[kinds_a == k])) for k in ("exp", "inv", "gauss_decay")},
+                           rank_mismatch_learned_vs_plain=mism, sampled_oracle_rank_mismatch=nbad,
+                           max_err_est=float(learned["err"][ok].max()), model=model.stats,
+                           train_s=train_s, generation_s=gen_s,
+                           stage_ms_per_step={k: v["ms"] / args.steps for k, v in lp.items()}),
+               roofline=roof)
+    return res
+
+
+WORKLOADS = {"c1": run_c1, "c2": run_c2, "c3": run_c3, "c4": run_c4, "c5": run_c5}
 
 
 def main():
@@ -359,6 +477,7 @@ def main():
     ap.add_argument("--workload", default="c1", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
     ap.add_argument("--block-w", type=int, default=0, choices=(0, 8, 16, 32), help="0 = autotuned")
+    ap.add_argument("--c5-count", type=int, default=100000)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on exactly one GPU; --gpus %d is not supported "

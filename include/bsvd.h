@@ -58,7 +58,11 @@ enum {
 /* Flags for batched_rsvd. */
 enum {
     BSVD_RSVD_FIXED = 1u << 0,  /* exactly ell0[b] samples, no adaptive growth (Algorithm 4 as printed) */
-    BSVD_RSVD_LEARNED = 1u << 1 /* initial sample count from the context's rank model */
+    BSVD_RSVD_LEARNED = 1u << 1, /* initial sample count from the context's rank model */
+    BSVD_RSVD_MIXED = 1u << 2    /* sketch products Y = A Omega in FP32 (Omega drawn in FP32, A rounded
+                                    to FP32 on load, FP32 accumulation); the basis QR, the projection
+                                    B = Q^T A, the exact check, the rank rule and the small SVD stay
+                                    in FP64, so the FP64 check still guarantees the tolerance */
 };
 
 /* Create a context bound to `device` (HIP ordinal) and `stream` (a hipStream_t; NULL = the null

@@ -28,6 +28,7 @@ SVD_BLOCK_W16 = 1 << 8
 
 RSVD_FIXED = 1 << 0
 RSVD_LEARNED = 1 << 1
+RSVD_MIXED = 1 << 2
 
 _lib = None
 

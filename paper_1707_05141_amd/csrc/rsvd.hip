@@ -62,7 +62,11 @@ __global__ __launch_bounds__(256) void rng_kernel(const RngDesc *__restrict__ d,
     const int idx = tl.y * 256 + threadIdx.x;
     const int r = idx / D.b, j = idx - (idx / D.b) * D.b;
     if (r >= D.n) return;
-    D.out[(size_t)r * D.ld + j] = gauss_entry(seed, (uint32_t)D.inst, (uint32_t)(D.col0 + j), (uint32_t)r);
+    const double z = gauss_entry(seed, (uint32_t)D.inst, (uint32_t)(D.col0 + j), (uint32_t)r);
+    if (D.f32)
+        static_cast<float *>(D.out)[(size_t)r * D.ld + j] = (float)z;
+    else
+        static_cast<double *>(D.out)[(size_t)r * D.ld + j] = z;
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -76,25 +80,26 @@ __device__ __forceinline__ double wave_sum(double v) {
 // or row-major (ytrans = 1, element (k, j) at Y[k * ldy + j]). One 64-lane workgroup per 64-row
 // tile; N <= NMAX.
 // ---------------------------------------------------------------------------------------------
-template <int NMAX>
+template <int NMAX, typename TA = double>
 __global__ __launch_bounds__(64) void gemm_nn_kernel(const MMDesc *__restrict__ d, const int2 *__restrict__ tiles) {
     constexpr int KC = 64;
-    __shared__ double ys[KC * NMAX];
+    __shared__ TA ys[KC * NMAX];
     const int2 tl = tiles[blockIdx.x];
     const MMDesc D = d[tl.x];
     const int lane = threadIdx.x;
     const int r = tl.y * 64 + lane;
     const bool rok = r < D.M;
-    double acc[NMAX];
+    TA acc[NMAX];
 #pragma unroll
-    for (int j = 0; j < NMAX; ++j) acc[j] = 0.0;
+    for (int j = 0; j < NMAX; ++j) acc[j] = TA(0);
     double xs = 0.0;
+    const TA *Yp = static_cast<const TA *>(D.Y);
     for (int k0 = 0; k0 < D.K; k0 += KC) {
         const int kc = (D.K - k0) < KC ? (D.K - k0) : KC;
         for (int idx = lane; idx < kc * NMAX; idx += 64) {
             const int kk = idx / NMAX, j = idx - (idx / NMAX) * NMAX;
-            double y = 0.0;
-            if (j < D.N) y = D.ytrans ? D.Y[(size_t)(k0 + kk) * D.ldy + j] : D.Y[(k0 + kk) + (size_t)j * D.ldy];
+            TA y = TA(0);
+            if (j < D.N) y = D.ytrans ? Yp[(size_t)(k0 + kk) * D.ldy + j] : Yp[(k0 + kk) + (size_t)j * D.ldy];
             ys[idx] = y;
         }
         __syncthreads();
@@ -110,19 +115,21 @@ __global__ __launch_bounds__(64) void gemm_nn_kernel(const MMDesc *__restrict__ 
                 xs = fma(x1, x1, xs);
                 xs = fma(x2, x2, xs);
                 xs = fma(x3, x3, xs);
+                const TA y0 = (TA)x0, y1 = (TA)x1, y2 = (TA)x2, y3 = (TA)x3;
 #pragma unroll
                 for (int j = 0; j < NMAX; ++j) {
-                    acc[j] = fma(x0, ys[(kk + 0) * NMAX + j], acc[j]);
-                    acc[j] = fma(x1, ys[(kk + 1) * NMAX + j], acc[j]);
-                    acc[j] = fma(x2, ys[(kk + 2) * NMAX + j], acc[j]);
-                    acc[j] = fma(x3, ys[(kk + 3) * NMAX + j], acc[j]);
+                    acc[j] = fma(y0, ys[(kk + 0) * NMAX + j], acc[j]);
+                    acc[j] = fma(y1, ys[(kk + 1) * NMAX + j], acc[j]);
+                    acc[j] = fma(y2, ys[(kk + 2) * NMAX + j], acc[j]);
+                    acc[j] = fma(y3, ys[(kk + 3) * NMAX + j], acc[j]);
                 }
             }
             for (; kk < kc; ++kk) {
                 const double x = xp[(size_t)kk * D.ldx];
                 xs = fma(x, x, xs);
+                const TA y = (TA)x;
 #pragma unroll
-                for (int j = 0; j < NMAX; ++j) acc[j] = fma(x, ys[kk * NMAX + j], acc[j]);
+                for (int j = 0; j < NMAX; ++j) acc[j] = fma(y, ys[kk * NMAX + j], acc[j]);
             }
         }
         __syncthreads();
@@ -132,8 +139,9 @@ __global__ __launch_bounds__(64) void gemm_nn_kernel(const MMDesc *__restrict__ 
 #pragma unroll
         for (int j = 0; j < NMAX; ++j) {
             if (j < D.N) {
-                double* cp = D.C + r + (size_t)j * D.ldc;
-                const double v = D.beta != 0.0 ? fma(D.alpha, acc[j], D.beta * (*cp)) : D.alpha * acc[j];
+                double *cp = D.C + r + (size_t)j * D.ldc;
+                const double a = (double)acc[j];
+                const double v = D.beta != 0.0 ? fma(D.alpha, a, D.beta * (*cp)) : D.alpha * a;
                 *cp = v;
                 cs = fma(v, v, cs);
             }
@@ -187,7 +195,7 @@ __global__ __launch_bounds__(256) void gemm_tn_kernel(const MMDesc *__restrict__
         for (int idx = t; idx < RC * NMAX; idx += 256) {
             const int j = idx / RC, rr = idx - (idx / RC) * RC;
             double v = 0.0;
-            if (j < D.N && rr < rc) v = D.Y[(r0 + rr) + (size_t)j * D.ldy];
+            if (j < D.N && rr < rc) v = static_cast<const double *>(D.Y)[(r0 + rr) + (size_t)j * D.ldy];
             ys[rr][j] = v;
         }
         __syncthreads();
@@ -357,6 +365,18 @@ hipError_t launch_gemm_nn(int nmax, const MMDesc *d, const int2 *tiles, int ntil
         case 16: hipLaunchKernelGGL(gemm_nn_kernel<16>, dim3(ntiles), dim3(64), 0, st, d, tiles); break;
         case 32: hipLaunchKernelGGL(gemm_nn_kernel<32>, dim3(ntiles), dim3(64), 0, st, d, tiles); break;
         case 64: hipLaunchKernelGGL(gemm_nn_kernel<64>, dim3(ntiles), dim3(64), 0, st, d, tiles); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_gemm_nn_f32(int nmax, const MMDesc *d, const int2 *tiles, int ntiles, hipStream_t st) {
+    if (ntiles <= 0) return hipSuccess;
+    switch (nmax) {
+        case 8: hipLaunchKernelGGL((gemm_nn_kernel<8, float>), dim3(ntiles), dim3(64), 0, st, d, tiles); break;
+        case 16: hipLaunchKernelGGL((gemm_nn_kernel<16, float>), dim3(ntiles), dim3(64), 0, st, d, tiles); break;
+        case 32: hipLaunchKernelGGL((gemm_nn_kernel<32, float>), dim3(ntiles), dim3(64), 0, st, d, tiles); break;
+        case 64: hipLaunchKernelGGL((gemm_nn_kernel<64, float>), dim3(ntiles), dim3(64), 0, st, d, tiles); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -7,14 +7,14 @@ namespace bsvd {
 
 // Omega block of one instance: n rows, b columns starting at counter column col0, row-major.
 struct RngDesc {
-    double *out;
-    int n, b, col0, ld, inst;
+    void *out;  // double, or float when f32 != 0
+    int n, b, col0, ld, inst, f32;
 };
 
 // One GEMM of the pipeline (see rsvd.hip for the two shapes).
 struct MMDesc {
     const double *X;
-    const double *Y;
+    const void *Y;  // double, or float for the FP32 sketch kernel
     double *C;
     double *xsq;  // nullable: per-tile partial sums of X^2 (gemm_nn only)
     double *csq;  // nullable: per-tile partial sums of the outputs' squares
@@ -41,6 +41,8 @@ struct GrowItem {
 
 hipError_t launch_rng(const RngDesc *d, const int2 *tiles, int ntiles, unsigned long long seed, hipStream_t st);
 hipError_t launch_gemm_nn(int nmax, const MMDesc *d, const int2 *tiles, int ntiles, hipStream_t st);
+// FP32 arithmetic variant of gemm_nn (X rounded to FP32, Y FP32, FP32 accumulation, C stored FP64).
+hipError_t launch_gemm_nn_f32(int nmax, const MMDesc *d, const int2 *tiles, int ntiles, hipStream_t st);
 hipError_t launch_gemm_tn(int nmax, const MMDesc *d, const int2 *tiles, int ntiles, hipStream_t st);
 hipError_t launch_grow_decide(RsvdState *st, const GrowItem *items, int count, int *flags, hipStream_t s);
 hipError_t launch_init_norm(RsvdState *st, const GrowItem *items, int count, hipStream_t s);

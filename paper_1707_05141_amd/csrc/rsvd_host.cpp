@@ -105,7 +105,7 @@ static int probe_features(Ctx *c, int batch, const int *m, const int *n, const v
     double skb = 0, skf = 0;
     for (int b = 0; b < batch; ++b) {
         const int kp = std::min(PROBE_COLS, std::min(m[b], n[b]));
-        hrd[b] = RngDesc{pb[b].Om, n[b], kp, PROBE_COL0, kp, b};
+        hrd[b] = RngDesc{pb[b].Om, n[b], kp, PROBE_COL0, kp, b, 0};
         for (int t = 0; t < cdiv(n[b] * kp, 256); ++t) rt.push_back(make_int2(b, t));
         MMDesc d;
         d.X = static_cast<const double *>(A[b]); d.Y = pb[b].Om; d.C = pb[b].Y; d.xsq = nullptr; d.csq = nullptr;
@@ -230,9 +230,10 @@ extern "C" int batched_rsvd(bsvd_ctx *ctx, int batch, const int *m, const int *n
     if ((flags & BSVD_RSVD_LEARNED) && (ell0 || (flags & BSVD_RSVD_FIXED)))
         return c->fail(BSVD_EARG, "BSVD_RSVD_LEARNED chooses ell0 itself (pass ell0 = NULL, no FIXED)");
     if ((flags & BSVD_RSVD_LEARNED) && !c->model) return c->fail(BSVD_EARG, "BSVD_RSVD_LEARNED needs a rank model");
-    if (flags & ~(unsigned)(BSVD_RSVD_FIXED | BSVD_RSVD_LEARNED))
+    if (flags & ~(unsigned)(BSVD_RSVD_FIXED | BSVD_RSVD_LEARNED | BSVD_RSVD_MIXED))
         return c->fail(BSVD_EUNSUP, "flags 0x%x not supported", flags);
     const bool learned = (flags & BSVD_RSVD_LEARNED) != 0;
+    const bool mixed = (flags & BSVD_RSVD_MIXED) != 0;
     hipError_t e = hipSetDevice(c->device);
     if (e != hipSuccess) return c->hip_fail(e, "hipSetDevice");
 
@@ -357,7 +358,7 @@ extern "C" int batched_rsvd(bsvd_ctx *ctx, int batch, const int *m, const int *n
     // Pack a set of GEMM descriptors grouped by NMAX together with their tile lists and launch them.
     struct Pending {
         int nmax;
-        int tn;
+        int tn;  // 0 nn, 1 tn, 2 nn with FP32 arithmetic
         MMDesc *d;
         int2 *tiles;
         int ntiles;
@@ -383,8 +384,9 @@ extern "C" int batched_rsvd(bsvd_ctx *ctx, int batch, const int *m, const int *n
     };
     auto launch_mm = [&](const std::vector<Pending> &v) -> int {
         for (const Pending &pd : v) {
-            hipError_t ee = pd.tn ? launch_gemm_tn(pd.nmax, pd.d, pd.tiles, pd.ntiles, c->stream)
-                                  : launch_gemm_nn(pd.nmax, pd.d, pd.tiles, pd.ntiles, c->stream);
+            hipError_t ee = pd.tn == 1   ? launch_gemm_tn(pd.nmax, pd.d, pd.tiles, pd.ntiles, c->stream)
+                            : pd.tn == 2 ? launch_gemm_nn_f32(pd.nmax, pd.d, pd.tiles, pd.ntiles, c->stream)
+                                         : launch_gemm_nn(pd.nmax, pd.d, pd.tiles, pd.ntiles, c->stream);
             if (ee != hipSuccess) return c->hip_fail(ee, "gemm launch");
         }
         return BSVD_OK;
@@ -467,7 +469,7 @@ extern "C" int batched_rsvd(bsvd_ctx *ctx, int batch, const int *m, const int *n
             for (size_t i = 0; i < init.size(); ++i) {
                 const int b = init[i];
                 Inst &q = I[b];
-                hrd[i] = RngDesc{dptr(q.oOm), q.n, q.ell0, 0, q.ell0, b};
+                hrd[i] = RngDesc{dptr(q.oOm), q.n, q.ell0, 0, q.ell0, b, mixed ? 1 : 0};
                 for (int t = 0; t < cdiv(q.n * q.ell0, 256); ++t) rt.push_back(make_int2((int)i, t));
                 MMGroup &g = sk[nmax_for(q.ell0)];
                 g.desc.push_back(mm_nn(static_cast<const double *>(A[b]), q.lda, dptr(q.oOm), q.ell0, 1, dptr(q.oY),
@@ -493,7 +495,7 @@ extern "C" int batched_rsvd(bsvd_ctx *ctx, int batch, const int *m, const int *n
             int2 *hrt = p.put<int2>(rt.size(), &drt);
             if (hrt) std::copy(rt.begin(), rt.end(), hrt);
             std::vector<Pending> mm;
-            pack_mm(p, sk, 0, mm);
+            pack_mm(p, sk, mixed ? 2 : 0, mm);
             QrDesc *dq;
             std::vector<std::pair<QKey, std::pair<const int *, int>>> ql;
             if ((rc = pack_qr(p, qv, ql, &dq))) return c->fail(rc, "internal: no QR kernel for the initial block");
@@ -545,7 +547,7 @@ extern "C" int batched_rsvd(bsvd_ctx *ctx, int batch, const int *m, const int *n
                     cgb += 2.0 * 8.0 * (2.0 * q.m * q.ell + 3.0 * q.m * blk + 2.0 * q.ell * blk);
                     cgf += 4.0 * 2.0 * q.m * (double)q.ell * blk;
                 }
-                hrd[i] = RngDesc{dptr(q.oOm), q.n, blk, q.ell, blk, b};
+                hrd[i] = RngDesc{dptr(q.oOm), q.n, blk, q.ell, blk, b, mixed ? 1 : 0};
                 for (int t = 0; t < cdiv(q.n * blk, 256); ++t) rt.push_back(make_int2(i, t));
                 MMGroup &g = sk[8];
                 g.desc.push_back(mm_nn(static_cast<const double *>(A[b]), q.lda, dptr(q.oOm), blk, 1, dptr(q.oY), q.m,
@@ -576,7 +578,7 @@ extern "C" int batched_rsvd(bsvd_ctx *ctx, int batch, const int *m, const int *n
             int2 *hrt = p.put<int2>(rt.size(), &drt);
             if (hrt) std::copy(rt.begin(), rt.end(), hrt);
             std::vector<Pending> msk, mt1, mn1, mt2, mn2;
-            pack_mm(p, sk, 0, msk);
+            pack_mm(p, sk, mixed ? 2 : 0, msk);
             pack_mm(p, tn1, 1, mt1);
             pack_mm(p, nn1, 0, mn1);
             pack_mm(p, tn2, 1, mt2);
@@ -779,7 +781,7 @@ extern "C" int bsvd_sample_omega(bsvd_ctx *ctx, unsigned long long seed, int ins
     rc = c->ensure_host(up.off);
     if (rc) return rc;
     char *hb = static_cast<char *>(c->hws);
-    *reinterpret_cast<RngDesc *>(hb + od) = RngDesc{out, n, b, col0, b, inst};
+    *reinterpret_cast<RngDesc *>(hb + od) = RngDesc{out, n, b, col0, b, inst, 0};
     int2 *ht = reinterpret_cast<int2 *>(hb + ot);
     for (int t = 0; t < nt; ++t) ht[t] = make_int2(0, t);
     if ((rc = c->upload(up.off))) return rc;

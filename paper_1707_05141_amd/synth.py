@@ -155,3 +155,56 @@ def kernel_blocks_packed(m, n, seed, kind="exp", corr=0.1, device="cuda", first_
                 o = int(offs[i])
                 buf[o:o + mm * nn] = flat[j]
     return buf, offs
+
+
+def c5_mixture(count, seed, sizes=SIZES_UNEVEN):
+    """Shapes, kinds and widths of the mixed batch: m, n uniform on `sizes`; kinds exp / inv /
+    gauss_decay in equal thirds in a seeded random order; gauss_decay width w ~ U[4, 64]."""
+    m, n = uneven_shapes(count, seed, sizes)
+    rng = _rng(seed, 0, 13)
+    kinds = np.array(["exp", "inv", "gauss_decay"])[rng.permutation(np.arange(count) % 3)]
+    w = rng.uniform(4.0, 64.0, size=count)
+    return m, n, kinds, w
+
+
+def mixed_blocks_packed(m, n, kinds, w, seed, device="cuda"):
+    """The mixed batch packed column-major (256-byte aligned) on `device`. Kernel blocks as in
+    kernel_blocks_packed; gauss_decay blocks U diag(exp(-(i/w)^2)) V^T with Haar U (m x k), V (n x k)
+    from torch's QR of Gaussian matrices (sign of diag(R) folded in), drawn per (m, n) group from a
+    generator seeded by (seed, m, n)."""
+    import torch
+    m = np.asarray(m, dtype=np.int64)
+    n = np.asarray(n, dtype=np.int64)
+    kinds = np.asarray(kinds)
+    buf, offs = kernel_blocks_packed(m, n, seed, kind=["exp" if k == "exp" else "inv" for k in kinds], device=device)
+    gd = np.nonzero(kinds == "gauss_decay")[0]
+    groups = {}
+    for i in gd:
+        groups.setdefault((int(m[i]), int(n[i])), []).append(int(i))
+    for (mm, nn), idx in sorted(groups.items()):
+        k = min(mm, nn)
+        gen = torch.Generator(device=device)
+        gen.manual_seed((int(seed) * 1000003 + mm * 1009 + nn) & 0x7FFFFFFFFFFFFFFF)
+        for s0 in range(0, len(idx), 256):
+            part = idx[s0:s0 + 256]
+            B = len(part)
+            G1 = torch.randn((B, mm, k), generator=gen, dtype=torch.float64, device=device)
+            G2 = torch.randn((B, nn, k), generator=gen, dtype=torch.float64, device=device)
+            Q1, R1 = torch.linalg.qr(G1)
+            Q2, R2 = torch.linalg.qr(G2)
+            d1 = torch.sign(torch.diagonal(R1, dim1=-2, dim2=-1))
+            d2 = torch.sign(torch.diagonal(R2, dim1=-2, dim2=-1))
+            d1[d1 == 0] = 1.0
+            d2[d2 == 0] = 1.0
+            Uh = Q1 * d1[:, None, :]
+            Vh = Q2 * d2[:, None, :]
+            ww = torch.from_numpy(np.asarray(w)[part]).to(device)
+            i1 = torch.arange(1, k + 1, dtype=torch.float64, device=device)
+            sig = torch.exp(-((i1[None, :] / ww[:, None]) ** 2))
+            # column-major storage of A = (U sigma) V^T is the row-major [n, m] array V (U sigma)^T
+            At = torch.bmm(Vh.contiguous(), (Uh * sig[:, None, :]).transpose(1, 2).contiguous())
+            flat = At.reshape(B, -1)
+            for j, i in enumerate(part):
+                o = int(offs[i])
+                buf[o:o + mm * nn] = flat[j]
+    return buf, offs

@@ -145,3 +145,32 @@ def test_rsvd_bitwise_reproducible_and_bad_args():
         P.rsvd_packed(buf, offs, m, n, eps=0.0)
     with pytest.raises(P.BsvdError):
         P.batched_rsvd([600], [4], [buf.data_ptr()], [600], [4], [buf.data_ptr()])
+
+
+@pytest.mark.parametrize("fixed", [False, True])
+def test_rsvd_mixed_precision_meets_eps(fixed):
+    """FP32 sketch products: the FP64 check keeps ||A - U S V^T||_F <= eps ||A||_F; ranks and singular
+    values agree with the plain FP64 run (the stated error of the mixed path)."""
+    rng = np.random.default_rng(8)
+    shapes = [(int(rng.choice([64, 128, 256])), int(rng.choice([64, 128, 256]))) for _ in range(24)]
+    mats = _kernel_batch(shapes, seed=41)
+    buf, offs, m, n = P.pack_colmajor(mats)
+    kw = dict(eps=EPS, max_rank=64, seed=5)
+    if fixed:
+        kw.update(flags=_lib.RSVD_FIXED, ell0=np.full(len(mats), 28))
+    plain = P.rsvd_packed(buf, offs, m, n, **kw)
+    kw["flags"] = kw.get("flags", 0) | _lib.RSVD_MIXED
+    mixed = P.rsvd_packed(buf, offs, m, n, **kw)
+    torch.cuda.synchronize()
+    worst = 0.0
+    for b, A in enumerate(mats):
+        mm, nn = A.shape
+        S, U, V = _unpack(mixed, mm, nn, b)
+        Sp, _, _ = _unpack(plain, mm, nn, b)
+        rel = np.linalg.norm(A - (U * S) @ V.T) / np.linalg.norm(A)
+        assert rel <= EPS, (b, rel)
+        assert len(S) == len(Sp) or _ambiguous(A, EPS, len(Sp))
+        k = min(len(S), len(Sp))
+        worst = max(worst, float(np.max(np.abs(S[:k] - Sp[:k])) / Sp[0]))
+    print("mixed vs FP64 sigma difference: %.2e sigma_max" % worst)
+    assert worst <= 1e-6
