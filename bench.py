@@ -92,6 +92,40 @@ def run_c1(args, torch, P, synth):
     return res
 
 
+def log(msg):
+    """Progress line on stderr (the JSON result is the only line on stdout)."""
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+KERNEL_BOUND = (("gemm_nn_kernel", "hbm"), ("gemm_tn_kernel", "hbm"), ("bj_gram_kernel", "mfma"),
+                ("bj_apply_kernel", "mfma"), ("qr_kernel", "alu"), ("jacobi_", "alu"))
+
+
+def kernel_roofline(kern, steps):
+    """Roofline entry of the kernel instantiation with the largest total time in the per-launch
+    profile `kern` ({name: dict(ms, bytes, flops, launches)}), plus the top of the kernel table."""
+    ranked = sorted(kern.items(), key=lambda kv: -kv[1]["ms"])
+    name, k = ranked[0]
+    bound = next((b for pre, b in KERNEL_BOUND if name.startswith(pre)), "alu")
+    if bound == "alu" and k["flops"] == 0:
+        bound = "hbm"  # no flop model (data-dependent sweeps): report its algorithmic bytes
+    avg_ms = k["ms"] / k["launches"]
+    if bound == "hbm":
+        per = k["bytes"] / k["launches"]
+        ach, peak, unit = per / (avg_ms * 1e-3) / 1e9, HBM_PEAK_GBS, "GB/s"
+    else:
+        per = k["flops"] / k["launches"]
+        ach = per / (avg_ms * 1e-3) / 1e12
+        peak = FP64_PEAK_TFLOPS if bound == "alu" else FP64_PEAK_TFLOPS
+        unit = "TFLOP/s"
+    roof = dict(bound=bound, achieved=ach, peak=peak, unit=unit, frac=ach / peak, traffic=None, kernel=name,
+                kernel_avg_ms=avg_ms, launches_per_step=k["launches"] / steps,
+                algorithmic_per_launch=per, algorithmic_unit="bytes" if bound == "hbm" else "flops")
+    table = [dict(kernel=n, stage=v["stage"], ms_per_step=v["ms"] / steps, launches_per_step=v["launches"] / steps,
+                  avg_ms=v["ms"] / v["launches"]) for n, v in ranked[:10]]
+    return roof, table
+
+
 def cpu_baseline_jacobi(A_np, oracle):
     """The oracle (OpenMP across instances, as written) on the same batch: SVDs/s."""
     b = A_np.shape[0]
@@ -219,6 +253,7 @@ def run_c4(args, torch, P, synth):
         ev[i][1].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    kern = P.profile_kernels()
     prof = P.profile_read()
     P.profile_enable(False)
     ms_per_step = wall * 1e3 / args.steps
@@ -246,10 +281,7 @@ def run_c4(args, torch, P, synth):
         nbad += int(k != ref["rank"])
     per = {k: v["ms"] / args.steps for k, v in prof.items()}
     flops = sum(v["flops"] for v in prof.values()) / args.steps
-    dom = max(("sketch", "project", "cgs", "qr", "jacobi", "output"), key=lambda s: prof[s]["ms"])
-    dom_ms = prof[dom]["ms"] / max(1, prof[dom]["launches"])
-    dom_bytes = prof[dom]["bytes"] / max(1, prof[dom]["launches"])
-    achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
+    roof, table = kernel_roofline(kern, args.steps)
     a_bytes = float((8 * m.astype(np.float64) * n).sum())
     res = dict(value=count / (ms_per_step * 1e-3), unit="SVDs/s", ms_per_step=ms_per_step, dtype="f64",
                config=dict(workload="rsvd_f64_adaptive_20000_exp_blocks_m_n_in_64_512", batch=count, eps=eps,
@@ -258,9 +290,8 @@ def run_c4(args, torch, P, synth):
                            passes_over_A=(prof["sketch"]["bytes"] + prof["project"]["bytes"]) / args.steps / a_bytes,
                            mean_rank=float(rank.mean()), max_err_est=float(err.max()),
                            sampled_rank_mismatch=nbad, generation_s=gen_s),
-               roofline=dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
-                             frac=achieved / HBM_PEAK_GBS, traffic=None, kernel="stage:" + dom,
-                             kernel_ms=dom_ms, bytes_per_launch=dom_bytes))
+               roofline=roof)
+    res["config"]["kernels"] = table
     if args.cpu_baseline:
         res["cpu_baseline"] = cpu_baseline_rsvd(m, n, dseed, oseed, eps, max_rank, synth, oracle)
     return res
@@ -353,7 +384,8 @@ def run_c5(args, torch, P, synth):
     and U diag(exp(-(i/w)^2)) V^T blocks (Haar U, V, w ~ U[4, 64]) in equal thirds; m, n uniform on
     {64, 128, 256, 512}; randomized SVD to relative Frobenius error 1e-6. The rank network is trained
     first (outside the timed region) on 6,000 blocks of the same mixture drawn with another seed; then
-    the learned sample count (value) and the plain adaptive finder are timed on the same batch."""
+    four variants run on the same batch: plain FP64 adaptive finder, FP32 sketch products (mixed),
+    learned initial sample count, and learned + mixed (the reported value)."""
     import oracle
     from paper_1707_05141_amd import _lib, rankmodel
     count = args.c5_count
@@ -362,16 +394,19 @@ def run_c5(args, torch, P, synth):
     t0 = time.perf_counter()
     tm, tn, tk, tw = synth.c5_mixture(6000, seed=501)
     tbuf, toffs = synth.mixed_blocks_packed(tm, tn, tk, tw, seed=501)
+    log("training set generated (%.1f s)" % (time.perf_counter() - t0))
     model = rankmodel.train_packed(tbuf, toffs, tm, tn, eps=eps, seed=11, epochs=60)
     del tbuf
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
+    log("rank network trained (%.1f s total, margin %.2f)" % (train_s, model.stats["margin"]))
     # ---- benchmark batch
     t0 = time.perf_counter()
     m, n, kinds, w = synth.c5_mixture(count, seed=5)
-    buf, offs = synth.mixed_blocks_packed(m, n, kinds, w, seed=5)
+    buf, offs = synth.mixed_blocks_packed(m, n, kinds, w, seed=5, progress=lambda t: log("generation: " + t))
     torch.cuda.synchronize()
     gen_s = time.perf_counter() - t0
+    log("batch of %d blocks generated (%.1f s, %.1f GB)" % (count, gen_s, buf.numel() * 8 / 1e9))
     o = _rsvd_buffers(torch, m, n, max_rank)
     samples = torch.zeros(count, dtype=torch.int32, device="cuda")
     A_ptrs = buf.data_ptr() + 8 * offs.astype(np.uint64)
@@ -381,7 +416,7 @@ def run_c5(args, torch, P, synth):
     eps_a = np.full(count, eps)
     a_bytes = float((8 * m.astype(np.float64) * n).sum())
 
-    def run(flags, steps, warmup):
+    def run(name, flags, steps, warmup):
         def step():
             P.batched_rsvd(m, n, A_ptrs, m, o["maxr"], S_ptrs, U_ptrs, m, V_ptrs, n, eps=eps_a, rank=o["rank"],
                            err_est=o["err"], info=o["info"], seed=oseed, flags=flags, samples=samples)
@@ -394,27 +429,29 @@ def run_c5(args, torch, P, synth):
             step()
         torch.cuda.synchronize()
         wall = (time.perf_counter() - t1) / steps
+        kern = P.profile_kernels()
         prof = P.profile_read()
         P.profile_enable(False)
-        info = o["info"].cpu().numpy()
-        rank = o["rank"].cpu().numpy()
-        err = o["err"].cpu().numpy()
-        return dict(ms=wall * 1e3, prof=prof, info=info, rank=rank, err=err, samples=samples.cpu().numpy().copy())
+        log("%s: %.1f ms per step over %d steps" % (name, wall * 1e3, steps))
+        return dict(ms=wall * 1e3, prof=prof, kern=kern, info=o["info"].cpu().numpy(), rank=o["rank"].cpu().numpy(),
+                    err=o["err"].cpu().numpy(), samples=samples.cpu().numpy().copy(), steps=steps)
 
     half = max(1, args.steps // 2)
-    variants = {"plain_fp64": (0, half), "mixed": (_lib.RSVD_MIXED, half), "learned_fp64": (_lib.RSVD_LEARNED, half),
-                "learned_mixed": (_lib.RSVD_LEARNED | _lib.RSVD_MIXED, args.steps)}
-    runs = {name: run(fl, st, 1 if name != "learned_mixed" else args.warmup) for name, (fl, st) in variants.items()}
+    variants = [("plain_fp64", 0, half, 1), ("mixed", _lib.RSVD_MIXED, half, 1),
+                ("learned_fp64", _lib.RSVD_LEARNED, half, 1),
+                ("learned_mixed", _lib.RSVD_LEARNED | _lib.RSVD_MIXED, args.steps, args.warmup)]
+    runs = {name: run(name, fl, st, wu) for name, fl, st, wu in variants}
     plain, learned = runs["plain_fp64"], runs["learned_mixed"]
-    ok = (learned["info"] == 0)
+    ok = learned["info"] == 0
     capped = learned["info"] == 2
-    assert np.all((learned["info"] == 0) | capped), np.bincount(learned["info"])
+    assert np.all(ok | capped), np.bincount(learned["info"])
     assert learned["err"][ok].max() <= eps
-    mism = int(np.sum((learned["rank"] != plain["rank"]) & ok & (plain["info"] == 0)))
-    # parity spot check: the result is checked by definition against the oracle (error <= eps and rank
-    # = the oracle's exact truncation rank from its full Jacobi SVD, for blocks the oracle finishes fast)
+    both = ok & (plain["info"] == 0)
+    diff = learned["rank"].astype(np.int64) - plain["rank"]
+    # parity spot check: error <= eps by definition, and the plain FP64 rank equals the oracle's exact
+    # truncation rank (full Jacobi SVD) on sampled blocks the oracle finishes fast
     rng = np.random.default_rng(2)
-    idx = rng.choice(np.nonzero(ok)[0], 12, replace=False)
+    idx = rng.choice(np.nonzero(both)[0], 12, replace=False)
     nbad = 0
     for i in idx:
         mi, ni = int(m[i]), int(n[i])
@@ -427,43 +464,70 @@ def run_c5(args, torch, P, synth):
         assert rel <= eps, (i, rel)
         if min(mi, ni) <= 128:
             S_full = oracle.jacobi_svd(A)[0]
-            nbad += int(k != oracle.rank_rule(S_full, float((A ** 2).sum()), eps)[0])
+            nbad += int(plain["rank"][i] != oracle.rank_rule(S_full, float((A ** 2).sum()), eps)[0])
+    log("parity spot check done")
 
-    def passes(r, steps):
-        return (r["prof"]["sketch"]["bytes"] + r["prof"]["project"]["bytes"]) / steps / a_bytes
+    def passes(r):
+        return (r["prof"]["sketch"]["bytes"] + r["prof"]["project"]["bytes"]) / r["steps"] / a_bytes
 
-    lp = learned["prof"]
-    dom = max(("sketch", "project", "cgs", "qr", "jacobi", "output"), key=lambda s: lp[s]["ms"])
-    dom_ms = lp[dom]["ms"] / max(1, lp[dom]["launches"])
-    dom_bytes = lp[dom]["bytes"] / max(1, lp[dom]["launches"])
-    bound = "hbm" if dom in ("sketch", "project") else "alu"
-    if bound == "hbm":
-        roof = dict(bound="hbm", achieved=dom_bytes / (dom_ms * 1e-3) / 1e9, peak=HBM_PEAK_GBS, unit="GB/s")
-    else:
-        fl = lp[dom]["flops"] / max(1, lp[dom]["launches"])
-        roof = dict(bound="alu", achieved=fl / (dom_ms * 1e-3) / 1e12, peak=FP64_PEAK_TFLOPS, unit="TFLOP/s")
-    roof.update(frac=roof["achieved"] / roof["peak"], traffic=None, kernel="stage:" + dom, kernel_ms=dom_ms,
-                bytes_per_launch=dom_bytes)
-    per_variant = {name: dict(ms=r["ms"], svds_per_s=count / (r["ms"] * 1e-3),
-                              passes_over_A=passes(r, variants[name][1]), mean_samples=float(r["samples"].mean()),
-                              max_err_est_ok=float(r["err"][r["info"] == 0].max()),
-                              info2_fraction=float(np.mean(r["info"] == 2)))
-                   for name, r in runs.items()}
+    roof, table = kernel_roofline(learned["kern"], learned["steps"])
     kinds_a = np.asarray(kinds)
+    per_variant = {name: dict(ms=r["ms"], svds_per_s=count / (r["ms"] * 1e-3), passes_over_A=passes(r),
+                              mean_samples=float(r["samples"].mean()),
+                              max_err_est_ok=float(r["err"][r["info"] == 0].max()),
+                              info2_fraction=float(np.mean(r["info"] == 2)),
+                              stage_ms_per_step={k: v["ms"] / r["steps"] for k, v in r["prof"].items()})
+                   for name, r in runs.items()}
+    flops = sum(v["flops"] for v in learned["prof"].values()) / learned["steps"]
     res = dict(value=count / (learned["ms"] * 1e-3), unit="SVDs/s", ms_per_step=learned["ms"], dtype="f32+f64",
-               config=dict(workload="rsvd_mixed_learned_100000_blocks_exp_inv_gaussdecay", batch=count, eps=eps,
-                           max_rank=max_rank, basis_cap=64,
+               config=dict(workload="rsvd_mixed_learned_100000_blocks_exp_inv_gaussdecay" if count == 100000 else
+                           "rsvd_mixed_learned_%d_blocks_exp_inv_gaussdecay" % count,
+                           batch=count, eps=eps, max_rank=max_rank, basis_cap=64,
                            precision="learned initial sample count + FP32 sketch products; FP64 basis QR, "
                                      "projection, check, rank rule and small SVD",
+                           gflop_per_s_model=flops / (learned["ms"] * 1e-3) / 1e9,
                            variants=per_variant, speedup_mixed_learned_vs_plain_fp64=plain["ms"] / learned["ms"],
                            info2_rank_above_cap_fraction=float(capped.mean()),
                            info2_by_kind={k: float(np.mean(capped[kinds_a == k])) for k in ("exp", "inv", "gauss_decay")},
-                           rank_mismatch_learned_vs_plain=mism, sampled_oracle_rank_mismatch=nbad,
-                           max_err_est=float(learned["err"][ok].max()), model=model.stats,
-                           train_s=train_s, generation_s=gen_s,
-                           stage_ms_per_step={k: v["ms"] / args.steps for k, v in lp.items()}),
+                           rank_learned_mixed_minus_plain=dict(
+                               blocks_compared=int(both.sum()),
+                               histogram={str(int(v)): int(c) for v, c in zip(*np.unique(diff[both], return_counts=True))}),
+                           sampled_oracle_rank_mismatch_plain=nbad, max_err_est=float(learned["err"][ok].max()),
+                           model=model.stats, train_s=train_s, generation_s=gen_s, kernels=table),
                roofline=roof)
+    if args.cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline_c5(buf, offs, m, n, kinds_a, oseed, eps, max_rank, oracle)
+        log("cpu baseline done")
     return res
+
+
+def cpu_baseline_c5(buf, offs, m, n, kinds, oseed, eps, max_rank, oracle):
+    """The oracle's plain FP64 adaptive randomized SVD on a stratified sample of the same batch (the
+    first 128 instances of each (kind, m, n) class: 6,144 blocks, the exact bytes the GPU factored),
+    threads across instances; SVDs/s of the sample."""
+    from concurrent.futures import ThreadPoolExecutor
+    picks = []
+    for kd in ("exp", "inv", "gauss_decay"):
+        for mm in (64, 128, 256, 512):
+            for nn in (64, 128, 256, 512):
+                hit = np.nonzero((kinds == kd) & (m == mm) & (n == nn))[0]
+                picks += [int(i) for i in hit[:128]]
+    mats = [buf[int(offs[i]):int(offs[i]) + int(m[i]) * int(n[i])].cpu().numpy().reshape(int(n[i]), int(m[i])).T.copy()
+            for i in picks]
+    threads = os.cpu_count() or 1
+
+    def one(j):
+        A = mats[j]
+        return oracle.rsvd_adaptive(A, seed=oseed, inst=picks[j], eps=eps, blk=8,
+                                    cap=min(A.shape[0], A.shape[1], 64), safety=2.0, max_rank=max_rank)["rank"]
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        list(ex.map(one, range(len(picks))))
+    dt = time.perf_counter() - t0
+    return dict(value=len(picks) / dt, unit="SVDs/s", cores=threads, kind="oracle",
+                sample="%d blocks: the first 128 of each (kind, m, n) class of the same batch, plain FP64 "
+                       "adaptive finder, %.1f s wall" % (len(picks), dt))
 
 
 WORKLOADS = {"c1": run_c1, "c2": run_c2, "c3": run_c3, "c4": run_c4, "c5": run_c5}
@@ -474,10 +538,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c1", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="c5", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
     ap.add_argument("--block-w", type=int, default=0, choices=(0, 8, 16, 32), help="0 = autotuned")
     ap.add_argument("--c5-count", type=int, default=100000)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (y = x * 1, FP64) five times: the reference "
+                         "kernel for scaling hardware byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on exactly one GPU; --gpus %d is not supported "
@@ -489,6 +556,16 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if args.copy_calibration:
+        nel = args.copy_calibration * (1 << 20) // 8
+        x = torch.ones(nel, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(5):
+            torch.mul(x, 1.0, out=y)
+        torch.cuda.synchronize()
+        print(json.dumps(dict(copy_calibration=True, read_bytes_per_launch=8 * nel, write_bytes_per_launch=8 * nel,
+                              launches=5)), flush=True)
+        return
     res = WORKLOADS[args.workload](args, torch, P, synth)
     out = dict(metric=METRIC, value=res["value"], unit=res["unit"], n_gpus=1, steps=args.steps, warmup=args.warmup,
                ms_per_step=res["ms_per_step"], higher_is_better=True, scaling="weak", vs_baseline=None,

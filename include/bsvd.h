@@ -101,6 +101,14 @@ int bsvd_profile_enable(bsvd_ctx *ctx, int on);
  * launch groups; all output arrays have `nstage` entries (nullable). Clears the records. */
 int bsvd_profile_read(bsvd_ctx *ctx, int nstage, double *ms, double *bytes, double *flops, int *launches);
 
+/* Per-kernel view of the records since the last enable/read (does not clear them; call it before
+ * bsvd_profile_read). Records that bracket exactly one kernel launch carry that kernel's name (its
+ * template instantiation, e.g. "qr_kernel<double, 64, 16, 32>"); they are summed per name, in order
+ * of first launch, as text lines "name<TAB>stage<TAB>ms<TAB>bytes<TAB>flops<TAB>launches\n".
+ * Writes the NUL-terminated text to buf (host, `cap` bytes) if it fits; returns the size it needs
+ * (including the NUL), or a negative error code. */
+int bsvd_profile_kernels(bsvd_ctx *ctx, char *buf, int cap);
+
 /* Autotuner cache. Without a BSVD_SVD_BLOCK_W* flag, the first batched_svd call that sends a
  * (dtype, M, N) class (M = max(m, n), N = min(m, n)) to the block path times widths 8, 16 and 32 on up
  * to 128 of its instances and keeps the fastest in the context (kind 0).

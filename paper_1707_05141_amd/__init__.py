@@ -128,6 +128,26 @@ def profile_enable(on=True, device=None):
     ctx.check(_lib.lib().bsvd_profile_enable(ctx.h, 1 if on else 0))
 
 
+def profile_kernels(device=None):
+    """Per-kernel sums of the records since the last enable/read (records are kept; read them with
+    profile_read afterwards): {kernel name: dict(stage, ms, bytes, flops, launches)} in launch order."""
+    import ctypes
+    ctx = _ctx(device if device is not None else torch.cuda.current_device())
+    need = _lib.lib().bsvd_profile_kernels(ctx.h, None, 0)
+    if need < 0:
+        ctx.check(need)
+    buf = ctypes.create_string_buffer(need)
+    got = _lib.lib().bsvd_profile_kernels(ctx.h, buf, need)
+    if got < 0 or got > need:
+        ctx.check(got if got < 0 else -1)
+    out = {}
+    for line in buf.value.decode().splitlines():
+        name, stage, ms, by, fl, la = line.split("\t")
+        out[name] = dict(stage=_lib.STAGES[int(stage)], ms=float(ms), bytes=float(by), flops=float(fl),
+                         launches=int(la))
+    return out
+
+
 def profile_read(device=None):
     """Per-stage sums since the last enable/read: {stage: dict(ms, bytes, flops, launches)}."""
     ctx = _ctx(device if device is not None else torch.cuda.current_device())

@@ -78,6 +78,7 @@ def lib():
                                     _vp]
     L.bsvd_profile_enable.argtypes = [_vp, ctypes.c_int]
     L.bsvd_profile_read.argtypes = [_vp, ctypes.c_int, _dp, _dp, _dp, _ip]
+    L.bsvd_profile_kernels.argtypes = [_vp, ctypes.c_char_p, ctypes.c_int]
     L.bsvd_tune_get.argtypes = [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _ip,
                                 ctypes.POINTER(ctypes.c_float), _ip, ctypes.c_int]
     L.bsvd_tune_save.argtypes = [_vp, ctypes.c_char_p]
@@ -89,6 +90,7 @@ def lib():
 def exported_symbols():
     return ["bsvd_create", "bsvd_destroy", "bsvd_last_error", "bsvd_sync", "bsvd_version", "batched_svd",
             "batched_qr", "batched_rsvd", "bsvd_sample_omega", "bsvd_profile_enable", "bsvd_profile_read",
+            "bsvd_profile_kernels",
             "bsvd_tune_get", "bsvd_tune_save", "bsvd_tune_load", "bsvd_rank_features", "bsvd_rank_model_nparam",
             "bsvd_rank_model_init", "bsvd_rank_model_set", "bsvd_rank_model_get", "bsvd_rank_model_save",
             "bsvd_rank_model_load", "bsvd_rank_model_forward", "bsvd_rank_model_loss_grad", "bsvd_rank_model_train"]

@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
 #include <cstring>
 #include <map>
 #include <vector>
@@ -96,7 +97,10 @@ int block_jacobi_run(Ctx *c, int dtype, int w, const std::vector<int> &insts, co
         if ((rc = c->upload_to(oMats, sizeof(BjMat) * (size_t)nm))) return rc;
     }
     hipError_t e;
-    int pi = c->prof_begin(BSVD_STAGE_JACOBI);
+    const char *tname = dtype ? "float" : "double";
+    char tag[96];
+    std::snprintf(tag, sizeof tag, "bj_init_kernel<%s>", tname);
+    int pi = c->prof_begin(BSVD_STAGE_JACOBI, tag);
     e = launch_bj_init(dtype, dmats, nm, c->stream);
     if (e != hipSuccess) return c->hip_fail(e, "block init launch");
     c->prof_end(pi, 0.0, 0.0);
@@ -172,20 +176,22 @@ int block_jacobi_run(Ctx *c, int dtype, int w, const std::vector<int> &insts, co
                 app_b += tasks_i * 2.0 * (double)esz * (h.M + h.NP) * K;
                 app_f += tasks_i * 2.0 * (h.M + h.NP) * (double)K * K;
             }
-            pi = c->prof_begin(BSVD_STAGE_SKETCH);
+            std::snprintf(tag, sizeof tag, "bj_gram_kernel<%s, %d>", tname, w);
+            pi = c->prof_begin(BSVD_STAGE_SKETCH, tag);
             e = launch_bj_gram(dtype, w, dmats, dt, (int)ntask, tol, c->stream);
             if (e != hipSuccess) return c->hip_fail(e, "block gram launch");
             c->prof_end(pi, gram_b, gram_f);
-            pi = c->prof_begin(BSVD_STAGE_JACOBI);
             JKey jk;
             if (choose_jacobi(0, K, K, 0, &jk)) return c->fail(BSVD_EUNSUP, "internal: no Jacobi kernel for G");
+            pi = c->prof ? c->prof_begin(BSVD_STAGE_JACOBI, kname_jacobi(0, jk).c_str()) : -1;
             if (jk.kind == JK_WAVE)
                 e = launch_jacobi_wave(0, jk.a, jk.b, dsd, dl, (int)ntask, 1e-15, 60, nullptr, nullptr, c->stream);
             else
                 e = launch_jacobi_lds(0, jk.a, jk.b, dsd, dl, (int)ntask, 1e-15, 60, nullptr, nullptr, c->stream);
             if (e != hipSuccess) return c->hip_fail(e, "block inner svd launch");
             c->prof_end(pi, 0.0, 0.0);
-            pi = c->prof_begin(BSVD_STAGE_OUTPUT);
+            std::snprintf(tag, sizeof tag, "bj_apply_kernel<%s, %d>", tname, w);
+            pi = c->prof_begin(BSVD_STAGE_OUTPUT, tag);
             e = launch_bj_apply(dtype, w, dmats, dt, (int)ntask, c->stream);
             if (e != hipSuccess) return c->hip_fail(e, "block apply launch");
             c->prof_end(pi, app_b, app_f);
@@ -196,7 +202,7 @@ int block_jacobi_run(Ctx *c, int dtype, int w, const std::vector<int> &insts, co
         for (size_t i = 0; i < active.size(); ++i) hl[i] = active[i];
         if ((rc = c->upload(sizeof(int) * active.size()))) return rc;
         const int *dl = reinterpret_cast<const int *>(db);
-        pi = c->prof_begin(BSVD_STAGE_SMALL);
+        pi = c->prof_begin(BSVD_STAGE_SMALL, "bj_sweep_kernel");
         e = launch_bj_sweep(dmats, dl, (int)active.size(), tol, dflags, c->stream);
         if (e != hipSuccess) return c->hip_fail(e, "block sweep launch");
         c->prof_end(pi, 0.0, 0.0);
@@ -222,7 +228,8 @@ int block_jacobi_run(Ctx *c, int dtype, int w, const std::vector<int> &insts, co
     int *hl = static_cast<int *>(c->hws);
     for (int i = 0; i < nm; ++i) hl[i] = i;
     if ((rc = c->upload(sizeof(int) * (size_t)nm))) return rc;
-    pi = c->prof_begin(BSVD_STAGE_SMALL);
+    std::snprintf(tag, sizeof tag, "bj_finalize_kernel<%s>", tname);
+    pi = c->prof_begin(BSVD_STAGE_SMALL, tag);
     e = launch_bj_finalize(dtype, dmats, reinterpret_cast<const int *>(db), nm, nmax, sweeps, info, max_sweeps,
                            c->stream);
     if (e != hipSuccess) return c->hip_fail(e, "block finalize launch");

@@ -98,7 +98,7 @@ int Ctx::upload_to(size_t dst_off, size_t bytes) {
     return BSVD_OK;
 }
 
-int Ctx::prof_begin(int stage) {
+int Ctx::prof_begin(int stage, const char *tag) {
     if (!prof) return -1;
     while ((int)evpool.size() < evused + 2) {
         hipEvent_t ev;
@@ -111,6 +111,7 @@ int Ctx::prof_begin(int stage) {
     r.ev1 = evused++;
     r.bytes = 0.0;
     r.flops = 0.0;
+    if (tag) r.tag = tag;
     hipEventRecord(evpool[r.ev0], stream);
     recs.push_back(r);
     return (int)recs.size() - 1;
@@ -271,6 +272,46 @@ int bsvd_profile_read(bsvd_ctx *ctx, int nstage, double *ms, double *bytes, doub
     c->recs.clear();
     c->evused = 0;
     return BSVD_OK;
+}
+
+int bsvd_profile_kernels(bsvd_ctx *ctx, char *buf, int cap) {
+    if (!ctx || cap < 0 || (cap > 0 && !buf)) return BSVD_EARG;
+    Ctx *c = reinterpret_cast<Ctx *>(ctx);
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return c->hip_fail(e, "hipStreamSynchronize");
+    struct Agg {
+        int stage;
+        double ms, bytes, flops;
+        int launches;
+    };
+    std::vector<std::string> order;
+    std::map<std::string, Agg> agg;
+    for (const Ctx::ProfRec &r : c->recs) {
+        if (r.tag.empty()) continue;
+        float t = 0.0f;
+        e = hipEventElapsedTime(&t, c->evpool[r.ev0], c->evpool[r.ev1]);
+        if (e != hipSuccess) return c->hip_fail(e, "hipEventElapsedTime");
+        auto it = agg.find(r.tag);
+        if (it == agg.end()) {
+            order.push_back(r.tag);
+            it = agg.emplace(r.tag, Agg{r.stage, 0.0, 0.0, 0.0, 0}).first;
+        }
+        it->second.ms += t;
+        it->second.bytes += r.bytes;
+        it->second.flops += r.flops;
+        it->second.launches += 1;
+    }
+    std::string out;
+    char line[512];
+    for (const std::string &k : order) {
+        const Agg &a = agg[k];
+        std::snprintf(line, sizeof line, "%s\t%d\t%.9g\t%.17g\t%.17g\t%d\n", k.c_str(), a.stage, a.ms, a.bytes, a.flops,
+                      a.launches);
+        out += line;
+    }
+    const int need = (int)out.size() + 1;
+    if (cap >= need) std::memcpy(buf, out.c_str(), (size_t)need);
+    return need;
 }
 
 const char *bsvd_version(void) { return "bsvd 0.1 (gfx950)"; }
@@ -545,27 +586,38 @@ int batched_svd(bsvd_ctx *ctx, int dtype, int batch, const int *m, const int *n,
     const int *djl = reinterpret_cast<const int *>(db + o_jl);
     const int *dql = reinterpret_cast<const int *>(db + o_ql);
     const int *dgl = reinterpret_cast<const int *>(db + o_gl);
-    double qr_fl = 0.0, qr_by = 0.0, j_by = 0.0, g_fl = 0.0, g_by = 0.0;
+    // algorithmic cost per launch: QR factorisation + thin Q (2 (2 M N^2 - 2 N^3 / 3) flops, A read,
+    // Q and R written); Jacobi reads the working matrix and writes U, V and sigma once
+    double g_fl = 0.0, g_by = 0.0;
     for (int b = 0; b < batch; ++b) {
-        if (is_blk[b]) continue;
+        if (is_blk[b] || !use_qr[b]) continue;
         const double M = m[b] >= n[b] ? m[b] : n[b], N = m[b] >= n[b] ? n[b] : m[b];
-        j_by += esz * (use_qr[b] ? N * N : M * N) + esz * (M * N + N * N + N);
-        if (use_qr[b]) {
-            qr_fl += 2.0 * (2.0 * M * N * N - 2.0 * N * N * N / 3.0);
-            qr_by += esz * (2.0 * M * N + N * N);
-            g_fl += 2.0 * M * N * N;
-            g_by += esz * (2.0 * M * N + N * N);
-        }
+        g_fl += 2.0 * M * N * N;
+        g_by += esz * (2.0 * M * N + N * N);
     }
-    int pidx = c->prof_begin(BSVD_STAGE_QR);
+    int pidx;
     for (auto &L : qlaunch) {
+        double by = 0.0, fl = 0.0;
+        for (int i = 0; i < L.second.second; ++i) {
+            const QrDesc &q = qd[ql[L.second.first + i]];
+            const double M = q.m, N = q.n;
+            fl += 2.0 * (2.0 * M * N * N - 2.0 * N * N * N / 3.0);
+            by += esz * ((q.Q ? 2.0 : 1.0) * M * N + N * N);
+        }
+        pidx = c->prof ? c->prof_begin(BSVD_STAGE_QR, kname_qr(dtype, L.first).c_str()) : -1;
         e = launch_qr(dtype, L.first.nb, L.first.seg, L.first.kr, dqd, dql + L.second.first, L.second.second,
                       c->stream);
         if (e != hipSuccess) return c->hip_fail(e, "qr launch");
+        c->prof_end(pidx, by, fl);
     }
-    c->prof_end(pidx, qr_by, qr_fl);
-    pidx = c->prof_begin(BSVD_STAGE_JACOBI);
     for (auto &L : jlaunch) {
+        double by = 0.0;
+        for (int i = 0; i < L.second.second; ++i) {
+            const int b = jl[L.second.first + i];
+            const double M = m[b] >= n[b] ? m[b] : n[b], N = m[b] >= n[b] ? n[b] : m[b];
+            by += esz * (use_qr[b] ? N * N : M * N) + esz * (M * N + N * N + N);
+        }
+        pidx = c->prof ? c->prof_begin(BSVD_STAGE_JACOBI, kname_jacobi(dtype, L.first).c_str()) : -1;
         if (L.first.kind == JK_WAVE)
             e = launch_jacobi_wave(dtype, L.first.a, L.first.b, dsd, djl + L.second.first, L.second.second, tol,
                                    max_sweeps, sweeps, info, c->stream);
@@ -573,10 +625,10 @@ int batched_svd(bsvd_ctx *ctx, int dtype, int batch, const int *m, const int *n,
             e = launch_jacobi_lds(dtype, L.first.a, L.first.b, dsd, djl + L.second.first, L.second.second, tol,
                                   max_sweeps, sweeps, info, c->stream);
         if (e != hipSuccess) return c->hip_fail(e, "jacobi launch");
+        c->prof_end(pidx, by, 0.0);
     }
-    c->prof_end(pidx, j_by, 0.0);
     if (!glist.empty()) {
-        pidx = c->prof_begin(BSVD_STAGE_OUTPUT);
+        pidx = c->prof_begin(BSVD_STAGE_OUTPUT, "gemm_small_kernel");
         e = launch_gemm_small(dtype, dgd, dgl, (int)glist.size(), c->stream);
         if (e != hipSuccess) return c->hip_fail(e, "gemm launch");
         c->prof_end(pidx, g_by, g_fl);
@@ -643,9 +695,18 @@ int batched_qr(bsvd_ctx *ctx, int dtype, int batch, const int *m, const int *n, 
     rc = c->upload(up.off);
     if (rc) return rc;
     for (auto &L : qlaunch) {
+        const int pidx = c->prof ? c->prof_begin(BSVD_STAGE_QR, kname_qr(dtype, L.first).c_str()) : -1;
         e = launch_qr(dtype, L.first.nb, L.first.seg, L.first.kr, reinterpret_cast<const QrDesc *>(db + o_qd),
                       reinterpret_cast<const int *>(db + o_ql) + L.second.first, L.second.second, c->stream);
         if (e != hipSuccess) return c->hip_fail(e, "qr launch");
+        double by = 0.0, fl = 0.0;
+        for (int i = 0; i < L.second.second; ++i) {
+            const QrDesc &q = qd[ql[L.second.first + i]];
+            const double M = q.m, N = q.n;
+            fl += 2.0 * M * N * N - 2.0 * N * N * N / 3.0 + (q.Q ? 2.0 * M * N * N - 2.0 * N * N * N / 3.0 : 0.0);
+            by += (dtype == BSVD_F64 ? 8.0 : 4.0) * (M * N + (q.Q ? M * N : 0.0) + (q.R ? N * N : 0.0));
+        }
+        c->prof_end(pidx, by, fl);
     }
     return BSVD_OK;
 }

@@ -50,18 +50,21 @@ struct Ctx {
     std::map<std::tuple<int, int, int, int>, int> tune;
     std::map<std::tuple<int, int, int, int>, std::vector<std::pair<int, float>>> tune_times;
 
-    // Per-stage profiling: HIP events recorded on `stream` around launch groups (off by default).
+    // Profiling: HIP events recorded on `stream` around launches (off by default). Each record
+    // names its stage and, when it brackets exactly one kernel launch, that kernel.
     struct ProfRec {
         int stage;
         int ev0, ev1;
         double bytes, flops;
+        std::string tag;
     };
     bool prof = false;
     std::vector<hipEvent_t> evpool;
     int evused = 0;
     std::vector<ProfRec> recs;
-    // Start a record for `stage`; returns its index or -1 when profiling is off.
-    int prof_begin(int stage);
+    // Start a record for `stage` (kernel name `tag`, nullable); returns its index or -1 when
+    // profiling is off.
+    int prof_begin(int stage, const char *tag = nullptr);
     // Close record `idx` with the algorithmic bytes / flops of the launches it brackets.
     void prof_end(int idx, double bytes, double flops);
 };

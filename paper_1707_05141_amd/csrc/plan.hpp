@@ -2,6 +2,8 @@
 #pragma once
 
 #include <cstddef>
+#include <cstdio>
+#include <string>
 
 #include "../../include/bsvd.h"
 #include "common.hpp"
@@ -60,6 +62,39 @@ inline int choose_jacobi(int dtype, int M, int N, unsigned flags, JKey *key) {
         return BSVD_EUNSUP;
     }
     return BSVD_OK;
+}
+
+// Flop model of one-sided Jacobi on an M x N working matrix that took `sweeps` sweeps: every sweep
+// tests the N (N - 1) / 2 pairs (three length-M dot products, 6 M flops); every sweep but the last
+// (which finds nothing to rotate) rotates them (6 M flops on the working columns, 6 N on V). Pairs
+// skipped below the threshold in earlier sweeps are not subtracted, so this is an upper bound.
+inline double jacobi_flops(int M, int N, int sweeps) {
+    const double P = 0.5 * N * (N - 1.0);
+    const double s = sweeps > 0 ? sweeps : 0;
+    return s * P * 6.0 * M + (s > 1 ? s - 1 : 0) * P * (6.0 * M + 6.0 * N);
+}
+
+// Names of kernel instantiations as the profiler reports them (the template arguments of the
+// kernel each launcher starts), used to tag per-launch profiling records.
+inline std::string kname_qr(int dtype, const QKey &k) {
+    char b[96];
+    std::snprintf(b, sizeof b, "qr_kernel<%s, %d, %d, %d>", dtype ? "float" : "double", k.nb, k.seg, k.kr);
+    return b;
+}
+inline std::string kname_jacobi(int dtype, const JKey &k) {
+    char b[96];
+    std::snprintf(b, sizeof b, "%s<%s, %d, %d>", k.kind == JK_WAVE ? "jacobi_wave_kernel" : "jacobi_lds_kernel",
+                  dtype ? "float" : "double", k.a, k.b);
+    return b;
+}
+// kind 0: gemm_nn FP64, 1: gemm_tn, 2: gemm_nn with FP32 arithmetic
+inline std::string kname_gemm(int kind, int nmax) {
+    char b[96];
+    if (kind == 1)
+        std::snprintf(b, sizeof b, "gemm_tn_kernel<%d>", nmax);
+    else
+        std::snprintf(b, sizeof b, "gemm_nn_kernel<%d, %s>", nmax, kind == 2 ? "float" : "double");
+    return b;
 }
 
 }  // namespace bsvd

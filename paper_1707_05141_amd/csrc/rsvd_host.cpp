@@ -75,6 +75,13 @@ struct MMGroup {
     std::vector<int> tiles_per;  // tiles of each descriptor
 };
 
+struct QLaunch {
+    QKey key;
+    const int *list;
+    int count;
+    double bytes, flops;
+};
+
 }  // namespace
 
 // Probe features of every instance: Y = A Omega_p (PROBE_COLS Gaussian columns at counter column
@@ -102,7 +109,7 @@ static int probe_features(Ctx *c, int batch, const int *m, const int *n, const v
     std::map<int, MMGroup> sk;
     std::vector<QrDesc> qv;
     std::map<QKey, std::vector<int>> qbins;
-    double skb = 0, skf = 0;
+    std::map<int, std::pair<double, double>> skcost;  // per NMAX: algorithmic bytes, flops
     for (int b = 0; b < batch; ++b) {
         const int kp = std::min(PROBE_COLS, std::min(m[b], n[b]));
         hrd[b] = RngDesc{pb[b].Om, n[b], kp, PROBE_COL0, kp, b, 0};
@@ -121,8 +128,8 @@ static int probe_features(Ctx *c, int batch, const int *m, const int *n, const v
         if (!qr_config(m[b], kp, &k.nb, &k.seg, &k.kr)) return c->fail(BSVD_EUNSUP, "instance %d: probe QR", b);
         qbins[k].push_back(b);
         hfd[b] = FeatDesc{pb[b].R, pb[b].ldr, kp, m[b], n[b], b};
-        skb += 8.0 * ((double)m[b] * n[b] + (double)(m[b] + n[b]) * kp);
-        skf += 2.0 * (double)m[b] * n[b] * kp;
+        skcost[nmax_for(kp)].first += 8.0 * ((double)m[b] * n[b] + (double)(m[b] + n[b]) * kp);
+        skcost[nmax_for(kp)].second += 2.0 * (double)m[b] * n[b] * kp;
     }
     int2 *drt;
     int2 *hrt = p.put<int2>(rt.size(), &drt);
@@ -130,13 +137,19 @@ static int probe_features(Ctx *c, int batch, const int *m, const int *n, const v
     QrDesc *dq;
     QrDesc *hq = p.put<QrDesc>(qv.size(), &dq);
     if (hq) std::copy(qv.begin(), qv.end(), hq);
-    std::vector<std::pair<QKey, std::pair<const int *, int>>> ql;
+    std::vector<QLaunch> ql;
     for (auto &kv : qbins) {
         int *dl;
         int *hl = p.put<int>(kv.second.size(), &dl);
         if (!hl) break;
         std::copy(kv.second.begin(), kv.second.end(), hl);
-        ql.push_back({kv.first, {dl, (int)kv.second.size()}});
+        double by = 0.0, fl = 0.0;
+        for (int b : kv.second) {
+            const double M = m[b], N = std::min(PROBE_COLS, std::min(m[b], n[b]));
+            fl += 2.0 * M * N * N - 2.0 * N * N * N / 3.0;  // factorisation only, R kept
+            by += 8.0 * (M * N + N * N);
+        }
+        ql.push_back(QLaunch{kv.first, dl, (int)kv.second.size(), by, fl});
     }
     std::vector<std::pair<MMDesc *, std::pair<int2 *, int>>> mm;
     std::vector<int> mmn;
@@ -158,23 +171,23 @@ static int probe_features(Ctx *c, int batch, const int *m, const int *n, const v
     }
     if (p.overflow) return c->fail(BSVD_EHIP, "internal: descriptor region overflow");
     if ((rc = c->upload_to(0, p.off))) return rc;
-    int pi = c->prof_begin(BSVD_STAGE_RNG);
+    int pi = c->prof_begin(BSVD_STAGE_RNG, "rng_kernel");
     hipError_t e = launch_rng(drd, drt, (int)rt.size(), seed, c->stream);
     if (e != hipSuccess) return c->hip_fail(e, "rng launch");
     c->prof_end(pi, 0.0, 0.0);
-    pi = c->prof_begin(BSVD_STAGE_SKETCH);
     for (size_t i = 0; i < mm.size(); ++i) {
+        pi = c->prof ? c->prof_begin(BSVD_STAGE_SKETCH, kname_gemm(0, mmn[i]).c_str()) : -1;
         e = launch_gemm_nn(mmn[i], mm[i].first, mm[i].second.first, mm[i].second.second, c->stream);
         if (e != hipSuccess) return c->hip_fail(e, "probe sketch launch");
+        c->prof_end(pi, skcost[mmn[i]].first, skcost[mmn[i]].second);
     }
-    c->prof_end(pi, skb, skf);
-    pi = c->prof_begin(BSVD_STAGE_QR);
     for (auto &L : ql) {
-        e = launch_qr(0, L.first.nb, L.first.seg, L.first.kr, dq, L.second.first, L.second.second, c->stream);
+        pi = c->prof ? c->prof_begin(BSVD_STAGE_QR, kname_qr(0, L.key).c_str()) : -1;
+        e = launch_qr(0, L.key.nb, L.key.seg, L.key.kr, dq, L.list, L.count, c->stream);
         if (e != hipSuccess) return c->hip_fail(e, "probe qr launch");
+        c->prof_end(pi, L.bytes, L.flops);
     }
-    c->prof_end(pi, 0.0, 0.0);
-    pi = c->prof_begin(BSVD_STAGE_SMALL);
+    pi = c->prof_begin(BSVD_STAGE_SMALL, "features_kernel");
     e = launch_features(dfd, batch, feats, c->stream);
     if (e != hipSuccess) return c->hip_fail(e, "features launch");
     c->prof_end(pi, 0.0, 0.0);
@@ -271,6 +284,7 @@ extern "C" int batched_rsvd(bsvd_ctx *ctx, int batch, const int *m, const int *n
     ar.off = dsz;
     const size_t oState = ar.alloc(sizeof(RsvdState) * (size_t)batch);
     const size_t oJinfo = ar.alloc(sizeof(int) * (size_t)batch);
+    const size_t oJsweeps = ar.alloc(sizeof(int) * (size_t)batch);
     const size_t oFlags = ar.alloc(sizeof(int) * (size_t)batch);
     const size_t oRankc = ar.alloc(sizeof(int) * (size_t)batch);
     const size_t oFeat = ar.alloc(sizeof(float) * MLP_IN * (size_t)batch);
@@ -298,11 +312,12 @@ extern "C" int batched_rsvd(bsvd_ctx *ctx, int batch, const int *m, const int *n
     if (rc) return rc;
     rc = c->ensure_host(std::max(dsz, sizeof(RsvdState) * (size_t)batch));
     if (rc) return rc;
-    rc = c->ensure_readback(sizeof(int) * (size_t)batch);
+    rc = c->ensure_readback(2 * sizeof(int) * (size_t)batch);
     if (rc) return rc;
     char *db = static_cast<char *>(c->dws);
     RsvdState *dstate = reinterpret_cast<RsvdState *>(db + oState);
     int *djinfo = reinterpret_cast<int *>(db + oJinfo);
+    int *djsweeps = reinterpret_cast<int *>(db + oJsweeps);
     int *dflags = reinterpret_cast<int *>(db + oFlags);
     int *drankc = reinterpret_cast<int *>(db + oRankc);
     const int *rb = static_cast<const int *>(c->rb);
@@ -362,6 +377,7 @@ extern "C" int batched_rsvd(bsvd_ctx *ctx, int batch, const int *m, const int *n
         MMDesc *d;
         int2 *tiles;
         int ntiles;
+        double bytes, flops;  // algorithmic: operands read once, result written once
     };
     auto pack_mm = [&](Packer &p, std::map<int, MMGroup> &groups, int tn, std::vector<Pending> &out) {
         for (auto &kv : groups) {
@@ -375,19 +391,29 @@ extern "C" int batched_rsvd(bsvd_ctx *ctx, int batch, const int *m, const int *n
             int2 *ht = p.put<int2>((size_t)nt, &dt);
             if (!hd || !ht) return;
             int k = 0;
+            double by = 0.0, fl = 0.0;
             for (size_t i = 0; i < g.desc.size(); ++i) {
-                hd[i] = g.desc[i];
+                const MMDesc &md = g.desc[i];
+                hd[i] = md;
                 for (int t = 0; t < g.tiles_per[i]; ++t) ht[k++] = make_int2((int)i, t);
+                const double M = md.M, N = md.N, K = md.K;
+                fl += 2.0 * M * N * K;
+                if (tn == 1)  // C (K x N) = X^T Y
+                    by += 8.0 * (M * K + M * N + K * N);
+                else  // C (M x N) = alpha X Y + beta C; the FP32 variant reads Y as FP32
+                    by += 8.0 * M * K + (tn == 2 ? 4.0 : 8.0) * K * N + 8.0 * M * N * (md.beta != 0.0 ? 2.0 : 1.0);
             }
-            out.push_back(Pending{kv.first, tn, dd, dt, nt});
+            out.push_back(Pending{kv.first, tn, dd, dt, nt, by, fl});
         }
     };
-    auto launch_mm = [&](const std::vector<Pending> &v) -> int {
+    auto launch_mm = [&](const std::vector<Pending> &v, int stage) -> int {
         for (const Pending &pd : v) {
+            const int pi = c->prof ? c->prof_begin(stage, kname_gemm(pd.tn, pd.nmax).c_str()) : -1;
             hipError_t ee = pd.tn == 1   ? launch_gemm_tn(pd.nmax, pd.d, pd.tiles, pd.ntiles, c->stream)
                             : pd.tn == 2 ? launch_gemm_nn_f32(pd.nmax, pd.d, pd.tiles, pd.ntiles, c->stream)
                                          : launch_gemm_nn(pd.nmax, pd.d, pd.tiles, pd.ntiles, c->stream);
             if (ee != hipSuccess) return c->hip_fail(ee, "gemm launch");
+            c->prof_end(pi, pd.bytes, pd.flops);
         }
         return BSVD_OK;
     };
@@ -398,9 +424,10 @@ extern "C" int batched_rsvd(bsvd_ctx *ctx, int batch, const int *m, const int *n
         d.M = M; d.N = N; d.K = K; d.ldx = ldx; d.ldy = ldy; d.ldc = ldc; d.ytrans = ytrans;
         return d;
     };
-    // QR launches grouped by kernel configuration
-    auto pack_qr = [&](Packer &p, const std::vector<QrDesc> &qv, std::vector<std::pair<QKey, std::pair<const int *, int>>> &out,
-                       QrDesc **dq) -> int {
+    // QR launches grouped by kernel configuration, with their algorithmic cost: Householder
+    // factorisation and formation of the thin Q (2 (2 m n^2 - 2 n^3 / 3) flops); A read, Q written,
+    // R written when asked for
+    auto pack_qr = [&](Packer &p, const std::vector<QrDesc> &qv, std::vector<QLaunch> &out, QrDesc **dq) -> int {
         std::map<QKey, std::vector<int>> bins;
         for (size_t i = 0; i < qv.size(); ++i) {
             QKey k;
@@ -414,16 +441,24 @@ extern "C" int batched_rsvd(bsvd_ctx *ctx, int batch, const int *m, const int *n
             int *dl;
             int *hl = p.put<int>(kv.second.size(), &dl);
             if (!hl) return BSVD_OK;
-            for (size_t i = 0; i < kv.second.size(); ++i) hl[i] = kv.second[i];
-            out.push_back({kv.first, {dl, (int)kv.second.size()}});
+            double by = 0.0, fl = 0.0;
+            for (size_t i = 0; i < kv.second.size(); ++i) {
+                hl[i] = kv.second[i];
+                const QrDesc &q = qv[kv.second[i]];
+                const double M = q.m, N = q.n;
+                fl += 2.0 * (2.0 * M * N * N - 2.0 * N * N * N / 3.0);
+                by += 8.0 * (M * N + (q.Q ? M * N : 0.0) + (q.R ? N * N : 0.0));
+            }
+            out.push_back(QLaunch{kv.first, dl, (int)kv.second.size(), by, fl});
         }
         return BSVD_OK;
     };
-    auto launch_qrs = [&](QrDesc *dq, const std::vector<std::pair<QKey, std::pair<const int *, int>>> &v) -> int {
+    auto launch_qrs = [&](QrDesc *dq, const std::vector<QLaunch> &v) -> int {
         for (auto &L : v) {
-            hipError_t ee = launch_qr(0, L.first.nb, L.first.seg, L.first.kr, dq, L.second.first, L.second.second,
-                                      c->stream);
+            const int pi = c->prof ? c->prof_begin(BSVD_STAGE_QR, kname_qr(0, L.key).c_str()) : -1;
+            hipError_t ee = launch_qr(0, L.key.nb, L.key.seg, L.key.kr, dq, L.list, L.count, c->stream);
             if (ee != hipSuccess) return c->hip_fail(ee, "qr launch");
+            c->prof_end(pi, L.bytes, L.flops);
         }
         return BSVD_OK;
     };
@@ -440,7 +475,7 @@ extern "C" int batched_rsvd(bsvd_ctx *ctx, int batch, const int *m, const int *n
         int *hc = static_cast<int *>(c->hws);
         for (int b = 0; b < batch; ++b) hc[b] = I[b].cap;
         if ((rc = c->upload_to(oCap, sizeof(int) * (size_t)batch))) return rc;
-        int pi = c->prof_begin(BSVD_STAGE_SMALL);
+        int pi = c->prof_begin(BSVD_STAGE_SMALL);  // forward network + ell0: two launches
         e = launch_mlp_forward(static_cast<const float *>(c->model), batch, dfeat, dpred, c->stream);
         if (e != hipSuccess) return c->hip_fail(e, "mlp forward launch");
         e = launch_ell0(dpred, dcap, batch, c->rank_margin, dflags, c->stream);
@@ -482,35 +517,24 @@ extern "C" int batched_rsvd(bsvd_ctx *ctx, int batch, const int *m, const int *n
                 hgi[i] = GrowItem{b, q.ell0, 1, 0};
                 q.ell = q.ell0;
             }
-            double skb = 0, skf = 0, rgb = 0, qrf = 0, qrb = 0;
-            for (int b : init) {
-                const Inst &q = I[b];
-                skb += 8.0 * ((double)q.m * q.n + (double)q.m * q.ell0 + (double)q.n * q.ell0);
-                skf += 2.0 * q.m * q.n * (double)q.ell0;
-                rgb += 8.0 * q.n * (double)q.ell0;
-                qrf += 4.0 * q.m * (double)q.ell0 * q.ell0;
-                qrb += 16.0 * q.m * (double)q.ell0;
-            }
+            double rgb = 0;
+            for (int b : init) rgb += (mixed ? 4.0 : 8.0) * I[b].n * (double)I[b].ell0;
             int2 *drt;
             int2 *hrt = p.put<int2>(rt.size(), &drt);
             if (hrt) std::copy(rt.begin(), rt.end(), hrt);
             std::vector<Pending> mm;
             pack_mm(p, sk, mixed ? 2 : 0, mm);
             QrDesc *dq;
-            std::vector<std::pair<QKey, std::pair<const int *, int>>> ql;
+            std::vector<QLaunch> ql;
             if ((rc = pack_qr(p, qv, ql, &dq))) return c->fail(rc, "internal: no QR kernel for the initial block");
             if ((rc = commit(p))) return rc;
-            int pi = c->prof_begin(BSVD_STAGE_RNG);
+            int pi = c->prof_begin(BSVD_STAGE_RNG, "rng_kernel");
             e = launch_rng(drd, drt, (int)rt.size(), seed, c->stream);
             if (e != hipSuccess) return c->hip_fail(e, "rng launch");
             c->prof_end(pi, rgb, 0.0);
-            pi = c->prof_begin(BSVD_STAGE_SKETCH);
-            if ((rc = launch_mm(mm))) return rc;
-            c->prof_end(pi, skb, skf);
-            pi = c->prof_begin(BSVD_STAGE_QR);
+            if ((rc = launch_mm(mm, BSVD_STAGE_SKETCH))) return rc;
             if ((rc = launch_qrs(dq, ql))) return rc;
-            c->prof_end(pi, qrb, qrf);
-            pi = c->prof_begin(BSVD_STAGE_SMALL);
+            pi = c->prof_begin(BSVD_STAGE_SMALL, "init_norm_kernel");
             e = launch_init_norm(dstate, dgi, (int)init.size(), c->stream);
             if (e != hipSuccess) return c->hip_fail(e, "init launch");
             c->prof_end(pi, 0.0, 0.0);
@@ -532,21 +556,13 @@ extern "C" int batched_rsvd(bsvd_ctx *ctx, int batch, const int *m, const int *n
             std::vector<int2> rt;
             std::map<int, MMGroup> sk, tn1, nn1, tn2, nn2;
             std::vector<QrDesc> qv;
-            double skb = 0, skf = 0, rgb = 0, qrf = 0, qrb = 0, cgb = 0, cgf = 0;
+            double rgb = 0;
             for (int i = 0; i < G; ++i) {
                 const int b = grow[i];
                 Inst &q = I[b];
                 const int blk = std::min(GROW_BLK, q.cap - q.ell);
                 const int first = q.ell == 0;
-                skb += 8.0 * ((double)q.m * q.n + (double)q.m * blk + (double)q.n * blk);
-                skf += 2.0 * q.m * q.n * (double)blk;
-                rgb += 8.0 * q.n * (double)blk;
-                qrf += 4.0 * q.m * (double)blk * blk;
-                qrb += 16.0 * q.m * (double)blk;
-                if (!first) {
-                    cgb += 2.0 * 8.0 * (2.0 * q.m * q.ell + 3.0 * q.m * blk + 2.0 * q.ell * blk);
-                    cgf += 4.0 * 2.0 * q.m * (double)q.ell * blk;
-                }
+                rgb += (mixed ? 4.0 : 8.0) * q.n * (double)blk;
                 hrd[i] = RngDesc{dptr(q.oOm), q.n, blk, q.ell, blk, b, mixed ? 1 : 0};
                 for (int t = 0; t < cdiv(q.n * blk, 256); ++t) rt.push_back(make_int2(i, t));
                 MMGroup &g = sk[8];
@@ -584,24 +600,19 @@ extern "C" int batched_rsvd(bsvd_ctx *ctx, int batch, const int *m, const int *n
             pack_mm(p, tn2, 1, mt2);
             pack_mm(p, nn2, 0, mn2);
             QrDesc *dq;
-            std::vector<std::pair<QKey, std::pair<const int *, int>>> ql;
+            std::vector<QLaunch> ql;
             if ((rc = pack_qr(p, qv, ql, &dq))) return c->fail(rc, "internal: no QR kernel for a sample block");
             if ((rc = commit(p))) return rc;
-            int pi = c->prof_begin(BSVD_STAGE_RNG);
+            int pi = c->prof_begin(BSVD_STAGE_RNG, "rng_kernel");
             e = launch_rng(drd, drt, (int)rt.size(), seed, c->stream);
             if (e != hipSuccess) return c->hip_fail(e, "rng launch");
             c->prof_end(pi, rgb, 0.0);
-            pi = c->prof_begin(BSVD_STAGE_SKETCH);
-            if ((rc = launch_mm(msk))) return rc;
-            c->prof_end(pi, skb, skf);
-            pi = c->prof_begin(BSVD_STAGE_CGS);
-            if ((rc = launch_mm(mt1)) || (rc = launch_mm(mn1)) || (rc = launch_mm(mt2)) || (rc = launch_mm(mn2)))
+            if ((rc = launch_mm(msk, BSVD_STAGE_SKETCH))) return rc;
+            if ((rc = launch_mm(mt1, BSVD_STAGE_CGS)) || (rc = launch_mm(mn1, BSVD_STAGE_CGS)) ||
+                (rc = launch_mm(mt2, BSVD_STAGE_CGS)) || (rc = launch_mm(mn2, BSVD_STAGE_CGS)))
                 return rc;
-            c->prof_end(pi, cgb, cgf);
-            pi = c->prof_begin(BSVD_STAGE_QR);
             if ((rc = launch_qrs(dq, ql))) return rc;
-            c->prof_end(pi, qrb, qrf);
-            pi = c->prof_begin(BSVD_STAGE_SMALL);
+            pi = c->prof_begin(BSVD_STAGE_SMALL, "grow_decide_kernel");
             e = launch_grow_decide(dstate, dgi, G, dflags, c->stream);
             if (e != hipSuccess) return c->hip_fail(e, "decide launch");
             c->prof_end(pi, 0.0, 0.0);
@@ -615,12 +626,9 @@ extern "C" int batched_rsvd(bsvd_ctx *ctx, int batch, const int *m, const int *n
             if ((rc = new_packer(p))) return rc;
             const int P = (int)pend_check.size();
             std::map<int, MMGroup> bt;
-            double pjb = 0, pjf = 0;
             for (int i = 0; i < P; ++i) {
                 const int b = pend_check[i];
                 const Inst &q = I[b];
-                pjb += 8.0 * ((double)q.m * q.n + (double)q.m * q.ell + (double)q.n * q.ell);
-                pjf += 2.0 * q.m * q.n * (double)q.ell;
                 MMGroup &g = bt[nmax_for(q.ell)];
                 g.desc.push_back(mm_nn(static_cast<const double *>(A[b]), q.lda, dptr(q.oQ), q.m, 0, dptr(q.oBt), q.n,
                                        q.m, q.ell, q.n, 1.0, 0.0, nullptr, dptr(q.oBsq)));
@@ -633,10 +641,8 @@ extern "C" int batched_rsvd(bsvd_ctx *ctx, int batch, const int *m, const int *n
             std::vector<Pending> mb;
             pack_mm(p, bt, 1, mb);
             if ((rc = commit(p))) return rc;
-            int pi = c->prof_begin(BSVD_STAGE_PROJECT);
-            if ((rc = launch_mm(mb))) return rc;
-            c->prof_end(pi, pjb, pjf);
-            pi = c->prof_begin(BSVD_STAGE_SMALL);
+            if ((rc = launch_mm(mb, BSVD_STAGE_PROJECT))) return rc;
+            int pi = c->prof_begin(BSVD_STAGE_SMALL, "check_kernel");
             e = launch_check(dstate, dl, P, dflags, c->stream);
             if (e != hipSuccess) return c->hip_fail(e, "check launch");
             c->prof_end(pi, 0.0, 0.0);
@@ -692,39 +698,51 @@ extern "C" int batched_rsvd(bsvd_ctx *ctx, int batch, const int *m, const int *n
             jl.push_back({kv.first, {djl, (int)kv.second.size()}});
         }
         QrDesc *dq;
-        std::vector<std::pair<QKey, std::pair<const int *, int>>> ql;
+        std::vector<QLaunch> ql;
         if ((rc = pack_qr(p, qv, ql, &dq))) return c->fail(rc, "internal: no QR kernel for B^T");
         if ((rc = commit(p))) return rc;
-        double qrf = 0, qrb = 0, jb_ = 0;
-        for (int b : finished) {
-            const Inst &q = I[b];
-            qrf += 2.0 * (2.0 * q.n * (double)q.ell * q.ell - 2.0 * (double)q.ell * q.ell * q.ell / 3.0);
-            qrb += 8.0 * (2.0 * q.n * (double)q.ell + (double)q.ell * q.ell);
-            jb_ += 8.0 * 4.0 * (double)q.ell * q.ell;
-        }
-        int pi = c->prof_begin(BSVD_STAGE_QR);
+        // Jacobi: R_B read, U_R and V_R written, sigma written
+        std::map<JKey, double> jbytes;
+        for (auto &kv : jb)
+            for (int i : kv.second) {
+                const double l = I[finished[i]].ell;
+                jbytes[kv.first] += 8.0 * (3.0 * l * l + l);
+            }
         if ((rc = launch_qrs(dq, ql))) return rc;
-        c->prof_end(pi, qrb, qrf);
-        pi = c->prof_begin(BSVD_STAGE_JACOBI);
+        int pi;
+        // profiled runs also read back the sweeps, to give each Jacobi record its flop count
+        std::vector<std::pair<int, const std::vector<int> *>> jrec;
         for (auto &L : jl) {
-            // info per descriptor position -> djinfo[position]
+            // info and sweeps per descriptor position -> djinfo[position], djsweeps[position]
+            pi = c->prof ? c->prof_begin(BSVD_STAGE_JACOBI, kname_jacobi(0, L.first).c_str()) : -1;
             if (L.first.kind == JK_WAVE)
-                e = launch_jacobi_wave(0, L.first.a, L.first.b, dsd, L.second.first, L.second.second, 1e-15, 60, nullptr,
-                                       djinfo, c->stream);
+                e = launch_jacobi_wave(0, L.first.a, L.first.b, dsd, L.second.first, L.second.second, 1e-15, 60,
+                                       djsweeps, djinfo, c->stream);
             else
-                e = launch_jacobi_lds(0, L.first.a, L.first.b, dsd, L.second.first, L.second.second, 1e-15, 60, nullptr,
-                                      djinfo, c->stream);
+                e = launch_jacobi_lds(0, L.first.a, L.first.b, dsd, L.second.first, L.second.second, 1e-15, 60,
+                                      djsweeps, djinfo, c->stream);
             if (e != hipSuccess) return c->hip_fail(e, "jacobi launch");
+            c->prof_end(pi, jbytes[L.first], 0.0);
+            if (pi >= 0) jrec.push_back({pi, &jb[L.first]});
         }
-        c->prof_end(pi, jb_, 0.0);
-        pi = c->prof_begin(BSVD_STAGE_SMALL);
+        pi = c->prof_begin(BSVD_STAGE_SMALL, "finalize_kernel");
         e = launch_finalize(dstate, dl, F, rank, err_est, info, djinfo, drankc, samples, c->stream);
         if (e != hipSuccess) return c->hip_fail(e, "finalize launch");
         c->prof_end(pi, 0.0, 0.0);
         e = hipMemcpyAsync(c->rb, drankc, sizeof(int) * (size_t)F, hipMemcpyDeviceToHost, c->stream);
         if (e != hipSuccess) return c->hip_fail(e, "hipMemcpyAsync(rank)");
+        if (!jrec.empty()) {
+            e = hipMemcpyAsync(static_cast<int *>(c->rb) + F, djsweeps, sizeof(int) * (size_t)F, hipMemcpyDeviceToHost,
+                               c->stream);
+            if (e != hipSuccess) return c->hip_fail(e, "hipMemcpyAsync(sweeps)");
+        }
         e = hipStreamSynchronize(c->stream);
         if (e != hipSuccess) return c->hip_fail(e, "hipStreamSynchronize");
+        for (auto &jr : jrec) {
+            double fl = 0.0;
+            for (int i : *jr.second) fl += jacobi_flops(I[finished[i]].ell, I[finished[i]].ell, rb[F + i]);
+            c->recs[jr.first].flops = fl;
+        }
     }
     // ---- back-transform U = Q U_R[:, :k], V = Q_B V_R[:, :k] ---------------------------------
     {
@@ -733,14 +751,11 @@ extern "C" int batched_rsvd(bsvd_ctx *ctx, int batch, const int *m, const int *n
         Packer p;
         if ((rc = new_packer(p))) return rc;
         std::map<int, MMGroup> out;
-        double ob = 0, of = 0;
         for (int i = 0; i < F; ++i) {
             const int b = finished[i];
             const Inst &q = I[b];
             const int k = kk[i];
             if (k <= 0) continue;
-            ob += 8.0 * ((double)(q.m + q.n) * q.ell + (double)(q.m + q.n) * k + 2.0 * q.ell * k);
-            of += 2.0 * (double)(q.m + q.n) * q.ell * k;
             MMGroup &g = out[nmax_for(k)];
             if (U && U[b]) {
                 g.desc.push_back(mm_nn(dptr(q.oQ), q.m, dptr(q.oUR), q.cap, 0, static_cast<double *>(U[b]), ldu[b], q.m,
@@ -756,9 +771,7 @@ extern "C" int batched_rsvd(bsvd_ctx *ctx, int batch, const int *m, const int *n
         std::vector<Pending> mo;
         pack_mm(p, out, 0, mo);
         if ((rc = commit(p))) return rc;
-        int pi = c->prof_begin(BSVD_STAGE_OUTPUT);
-        if ((rc = launch_mm(mo))) return rc;
-        c->prof_end(pi, ob, of);
+        if ((rc = launch_mm(mo, BSVD_STAGE_OUTPUT))) return rc;
     }
     return BSVD_OK;
 }

@@ -18,6 +18,8 @@ Haar matrices are the Q factor of a Gaussian matrix with the sign of diag(R) fol
 """
 from __future__ import annotations
 
+import os
+
 import numpy as np
 
 SIZES_UNEVEN = (64, 128, 256, 512)
@@ -138,7 +140,8 @@ def kernel_blocks_packed(m, n, seed, kind="exp", corr=0.1, device="cuda", first_
     kinds = kind if isinstance(kind, (list, tuple, np.ndarray)) else [kind] * len(m)
     groups = {}
     for i in range(len(m)):
-        groups.setdefault((int(m[i]), int(n[i]), kinds[i]), []).append(i)
+        if kinds[i] is not None:  # None: left zero for the caller to fill
+            groups.setdefault((int(m[i]), int(n[i]), kinds[i]), []).append(i)
     for (mm, nn, kd), idx in groups.items():
         for s0 in range(0, len(idx), 512):
             part = idx[s0:s0 + 512]
@@ -150,10 +153,9 @@ def kernel_blocks_packed(m, n, seed, kind="exp", corr=0.1, device="cuda", first_
             Yt = torch.from_numpy(Y).to(device)
             d = torch.sqrt(((Yt[:, :, None, :] - Xt[:, None, :, :]) ** 2).sum(-1))  # [B, n, m]: column-major
             blk = torch.exp(-d / corr) if kd == "exp" else 1.0 / d
-            flat = blk.reshape(len(part), -1)
-            for j, i in enumerate(part):
-                o = int(offs[i])
-                buf[o:o + mm * nn] = flat[j]
+            dst = torch.from_numpy(offs[part].astype(np.int64)).to(device)
+            cols = torch.arange(mm * nn, device=device)
+            buf[(dst[:, None] + cols[None, :]).reshape(-1)] = blk.reshape(-1)
     return buf, offs
 
 
@@ -167,44 +169,72 @@ def c5_mixture(count, seed, sizes=SIZES_UNEVEN):
     return m, n, kinds, w
 
 
-def mixed_blocks_packed(m, n, kinds, w, seed, device="cuda"):
+def _orth_haar(G):
+    """Q with positive diag(R) of each matrix of the stack G (B x rows x k, rows >= k, FP64): the Q
+    factor of a Gaussian matrix normalised this way is Haar distributed. Computed as Cholesky QR
+    applied twice (Q = G R^-1 with R^T R = G^T G; the second pass restores orthogonality to rounding
+    level); any matrix whose Cholesky factorisation fails or whose result is not orthonormal to 1e-13
+    is redone by Householder QR with the signs of diag(R) folded into Q."""
+    import torch
+    B, _, k = G.shape
+    Q = G
+    bad = torch.zeros(B, dtype=torch.bool, device=G.device)
+    for _ in range(2):
+        C = torch.bmm(Q.transpose(1, 2).contiguous(), Q)
+        L, info = torch.linalg.cholesky_ex(C)
+        bad |= info != 0
+        L[bad] = torch.eye(k, dtype=G.dtype, device=G.device)
+        Q = torch.linalg.solve_triangular(L, Q.transpose(1, 2).contiguous(), upper=False).transpose(1, 2).contiguous()
+    E = torch.bmm(Q.transpose(1, 2).contiguous(), Q) - torch.eye(k, dtype=G.dtype, device=G.device)
+    bad |= ~torch.isfinite(E).all(dim=(1, 2))
+    bad |= E.abs().amax(dim=(1, 2)) > 1e-13
+    if bad.any():
+        idx = torch.nonzero(bad).flatten()
+        Qh, Rh = torch.linalg.qr(G[idx])
+        d = torch.sign(torch.diagonal(Rh, dim1=-2, dim2=-1))
+        d[d == 0] = 1.0
+        Q[idx] = Qh * d[:, None, :]
+    return Q
+
+
+def mixed_blocks_packed(m, n, kinds, w, seed, device="cuda", chunk=256, progress=None):
     """The mixed batch packed column-major (256-byte aligned) on `device`. Kernel blocks as in
     kernel_blocks_packed; gauss_decay blocks U diag(exp(-(i/w)^2)) V^T with Haar U (m x k), V (n x k)
-    from torch's QR of Gaussian matrices (sign of diag(R) folded in), drawn per (m, n) group from a
-    generator seeded by (seed, m, n)."""
+    (orthonormal factors of Gaussian matrices, see _orth_haar), drawn per chunk of `chunk` blocks of
+    one (m, n) class (chunks formed in order of w) from a generator seeded by (seed, m, n, chunk).
+    Terms with exp(-(i/w)^2) < 1e-18 (i > 6.44 w) are left out: they change no entry of the block at
+    FP64 resolution, and the first k columns of a Haar factor are themselves Haar, so
+    k = min(m, n, ceil(6.44 w_max)) per chunk. `progress(text)` is called after each (m, n) class."""
     import torch
     m = np.asarray(m, dtype=np.int64)
     n = np.asarray(n, dtype=np.int64)
     kinds = np.asarray(kinds)
-    buf, offs = kernel_blocks_packed(m, n, seed, kind=["exp" if k == "exp" else "inv" for k in kinds], device=device)
+    w = np.asarray(w, dtype=np.float64)
+    buf, offs = kernel_blocks_packed(m, n, seed, kind=[None if k == "gauss_decay" else str(k) for k in kinds], device=device)
+    if progress:
+        progress("kernel blocks done")
     gd = np.nonzero(kinds == "gauss_decay")[0]
     groups = {}
     for i in gd:
         groups.setdefault((int(m[i]), int(n[i])), []).append(int(i))
     for (mm, nn), idx in sorted(groups.items()):
-        k = min(mm, nn)
-        gen = torch.Generator(device=device)
-        gen.manual_seed((int(seed) * 1000003 + mm * 1009 + nn) & 0x7FFFFFFFFFFFFFFF)
-        for s0 in range(0, len(idx), 256):
-            part = idx[s0:s0 + 256]
+        idx = sorted(idx, key=lambda i: (w[i], i))
+        for cid, s0 in enumerate(range(0, len(idx), chunk)):
+            part = idx[s0:s0 + chunk]
             B = len(part)
-            G1 = torch.randn((B, mm, k), generator=gen, dtype=torch.float64, device=device)
-            G2 = torch.randn((B, nn, k), generator=gen, dtype=torch.float64, device=device)
-            Q1, R1 = torch.linalg.qr(G1)
-            Q2, R2 = torch.linalg.qr(G2)
-            d1 = torch.sign(torch.diagonal(R1, dim1=-2, dim2=-1))
-            d2 = torch.sign(torch.diagonal(R2, dim1=-2, dim2=-1))
-            d1[d1 == 0] = 1.0
-            d2[d2 == 0] = 1.0
-            Uh = Q1 * d1[:, None, :]
-            Vh = Q2 * d2[:, None, :]
-            ww = torch.from_numpy(np.asarray(w)[part]).to(device)
+            k = int(min(mm, nn, np.ceil(6.44 * w[part].max())))
+            gen = torch.Generator(device=device)
+            gen.manual_seed((int(seed) * 1000003 + mm * 1009 + nn * 7 + cid * 7919) & 0x7FFFFFFFFFFFFFFF)
+            Uh = _orth_haar(torch.randn((B, mm, k), generator=gen, dtype=torch.float64, device=device))
+            Vh = _orth_haar(torch.randn((B, nn, k), generator=gen, dtype=torch.float64, device=device))
+            ww = torch.from_numpy(w[part]).to(device)
             i1 = torch.arange(1, k + 1, dtype=torch.float64, device=device)
             sig = torch.exp(-((i1[None, :] / ww[:, None]) ** 2))
             # column-major storage of A = (U sigma) V^T is the row-major [n, m] array V (U sigma)^T
             At = torch.bmm(Vh.contiguous(), (Uh * sig[:, None, :]).transpose(1, 2).contiguous())
-            flat = At.reshape(B, -1)
-            for j, i in enumerate(part):
-                o = int(offs[i])
-                buf[o:o + mm * nn] = flat[j]
+            dst = torch.from_numpy(offs[part].astype(np.int64)).to(device)
+            cols = torch.arange(mm * nn, device=device)
+            buf[(dst[:, None] + cols[None, :]).reshape(-1)] = At.reshape(-1)
+        if progress:
+            progress("gauss_decay %dx%d done (%d blocks)" % (mm, nn, len(idx)))
     return buf, offs
