@@ -287,9 +287,9 @@ double oracle_gauss(uint64_t seed, uint32_t inst, uint32_t col, uint32_t row) {
 /* subspace (zero for a full SVD) and the tail summed from the smallest sigma upward.          */
 /* ------------------------------------------------------------------------------------------ */
 int oracle_rank_rule(int nsig, const double *sigma, double normA2, double eps, double *tail_out) {
-    double tot = 0.0;
-    for (int i = nsig - 1; i >= 0; --i) tot += sigma[i] * sigma[i];
-    double resid2 = normA2 - tot;
+    long double tot = 0.0L; /* extended precision: resid2 is a small difference of large sums */
+    for (int i = nsig - 1; i >= 0; --i) tot += (long double)sigma[i] * sigma[i];
+    double resid2 = (double)((long double)normA2 - tot);
     if (resid2 < 0.0) resid2 = 0.0;
     double thr = eps * eps * normA2;
     /* tail[k] = resid2 + sum_{i>=k} sigma_i^2, built from the smallest upward */
@@ -313,11 +313,14 @@ int oracle_rank_rule(int nsig, const double *sigma, double normA2, double eps, d
 /* ------------------------------------------------------------------------------------------ */
 /* Randomized SVD helpers.                                                                     */
 /* ------------------------------------------------------------------------------------------ */
+/* ||A||_F^2 summed in extended precision: the a-posteriori check and the truncation compare
+ * differences of such sums with eps^2 ||A||_F^2 (1e-12 relative at eps = 1e-6), well below the
+ * drift of a plain double sum over 10^5 terms. */
 static double frob2(int m, int n, const double *A, int lda) {
-    double s = 0.0;
+    long double s = 0.0L;
     for (int j = 0; j < n; ++j)
-        for (int i = 0; i < m; ++i) s += A[i + (size_t)j * lda] * A[i + (size_t)j * lda];
-    return s;
+        for (int i = 0; i < m; ++i) s += (long double)A[i + (size_t)j * lda] * A[i + (size_t)j * lda];
+    return (double)s;
 }
 
 /* Y(:, 0:b) = A * Omega(:, col0 : col0+b) with Omega drawn from the counter generator. */
@@ -391,9 +394,9 @@ static int rsvd_second_phase(int m, int n, const double *A, int lda, const doubl
             /* capacity-limited: tail includes the dropped sigma */
             double tot = 0.0;
             for (int i = ell - 1; i >= kk; --i) tot += sg[i] * sg[i];
-            double all = 0.0;
-            for (int i = ell - 1; i >= 0; --i) all += sg[i] * sg[i];
-            double resid2 = normA2 - all;
+            long double all = 0.0L;
+            for (int i = ell - 1; i >= 0; --i) all += (long double)sg[i] * sg[i];
+            double resid2 = (double)((long double)normA2 - all);
             if (resid2 < 0) resid2 = 0;
             t = resid2 + tot;
         } else {
