@@ -286,10 +286,9 @@ double oracle_gauss(uint64_t seed, uint32_t inst, uint32_t col, uint32_t row) {
 /* with resid2 = max(0, normA2 - sum_i sigma_i^2) the part of ||A||_F^2 outside the factored  */
 /* subspace (zero for a full SVD) and the tail summed from the smallest sigma upward.          */
 /* ------------------------------------------------------------------------------------------ */
-int oracle_rank_rule(int nsig, const double *sigma, double normA2, double eps, double *tail_out) {
-    long double tot = 0.0L; /* extended precision: resid2 is a small difference of large sums */
-    for (int i = nsig - 1; i >= 0; --i) tot += (long double)sigma[i] * sigma[i];
-    double resid2 = (double)((long double)normA2 - tot);
+/* The rule with the residual given: resid2 + sum_{i >= k} sigma_i^2 <= eps^2 normA2. */
+static int rank_rule_resid(int nsig, const double *sigma, double resid2, double normA2, double eps,
+                           double *tail_out) {
     if (resid2 < 0.0) resid2 = 0.0;
     double thr = eps * eps * normA2;
     /* tail[k] = resid2 + sum_{i>=k} sigma_i^2, built from the smallest upward */
@@ -308,6 +307,12 @@ int oracle_rank_rule(int nsig, const double *sigma, double normA2, double eps, d
     }
     if (tail_out) *tail_out = tail_at_k;
     return k;
+}
+
+int oracle_rank_rule(int nsig, const double *sigma, double normA2, double eps, double *tail_out) {
+    long double tot = 0.0L; /* extended precision: resid2 is a small difference of large sums */
+    for (int i = nsig - 1; i >= 0; --i) tot += (long double)sigma[i] * sigma[i];
+    return rank_rule_resid(nsig, sigma, (double)((long double)normA2 - tot), normA2, eps, tail_out);
 }
 
 /* ------------------------------------------------------------------------------------------ */
@@ -368,8 +373,13 @@ static int rsvd_second_phase(int m, int n, const double *A, int lda, const doubl
     for (int j = 0; j < ell; ++j)
         for (int i = 0; i < ell; ++i) RBt[i + (size_t)j * ell] = RB[j + (size_t)i * ell];
     int info = oracle_jacobi_svd(ell, ell, RBt, ell, tol, 0, sg, UR, ell, VR, ell, NULL);
+    /* resid2 = ||A - Q Q^T A||_F^2 = ||A||_F^2 - ||B||_F^2 from the check's sums, not as
+     * ||A||_F^2 - sum_i sigma_i^2: equal in exact arithmetic, but the Jacobi rotations keep ||B||_F
+     * only to ~1e-14 relative, which is 5% of eps^2 at eps = 1e-6 */
+    double resid2 = normA2 - b2;
+    if (resid2 < 0.0) resid2 = 0.0;
     double tail;
-    int k = oracle_rank_rule(ell, sg, normA2, eps, &tail);
+    int k = rank_rule_resid(ell, sg, resid2, normA2, eps, &tail);
     int kk = k < max_rank ? k : max_rank;
     if (k > max_rank) info = ORACLE_INFO_RANKCAP;
     *rank = kk;
@@ -394,10 +404,6 @@ static int rsvd_second_phase(int m, int n, const double *A, int lda, const doubl
             /* capacity-limited: tail includes the dropped sigma */
             double tot = 0.0;
             for (int i = ell - 1; i >= kk; --i) tot += sg[i] * sg[i];
-            long double all = 0.0L;
-            for (int i = ell - 1; i >= 0; --i) all += (long double)sg[i] * sg[i];
-            double resid2 = (double)((long double)normA2 - all);
-            if (resid2 < 0) resid2 = 0;
             t = resid2 + tot;
         } else {
             t = tail;
