@@ -206,13 +206,14 @@ def run_c2(args, torch, P, synth):
 
 
 def _rsvd_buffers(torch, m, n, max_rank):
+    """Output buffers with room for min(m, n, max_rank) columns per instance."""
     b = len(m)
-    maxr = np.full(b, max_rank, dtype=np.int32)
+    maxr = np.minimum(np.minimum(m, n), max_rank).astype(np.int32)
     S = torch.zeros((b, max_rank), dtype=torch.float64, device="cuda")
-    u_off = np.concatenate([[0], np.cumsum(m.astype(np.int64) * max_rank)[:-1]]).astype(np.int64)
-    v_off = np.concatenate([[0], np.cumsum(n.astype(np.int64) * max_rank)[:-1]]).astype(np.int64)
-    U = torch.zeros(int((m.astype(np.int64) * max_rank).sum()), dtype=torch.float64, device="cuda")
-    V = torch.zeros(int((n.astype(np.int64) * max_rank).sum()), dtype=torch.float64, device="cuda")
+    u_off = np.concatenate([[0], np.cumsum(m.astype(np.int64) * maxr)[:-1]]).astype(np.int64)
+    v_off = np.concatenate([[0], np.cumsum(n.astype(np.int64) * maxr)[:-1]]).astype(np.int64)
+    U = torch.zeros(int((m.astype(np.int64) * maxr).sum()), dtype=torch.float64, device="cuda")
+    V = torch.zeros(int((n.astype(np.int64) * maxr).sum()), dtype=torch.float64, device="cuda")
     rank = torch.zeros(b, dtype=torch.int32, device="cuda")
     err = torch.zeros(b, dtype=torch.float64, device="cuda")
     info = torch.zeros(b, dtype=torch.int32, device="cuda")
@@ -354,15 +355,17 @@ def run_c3(args, torch, P, synth):
             call()
         torch.cuda.synchronize()
         wall = (time.perf_counter() - t0) / args.steps
+        kern = P.profile_kernels()
         prof = P.profile_read()
         P.profile_enable(False)
         err = float(np.max(np.abs(S.double().cpu().numpy() - sig[None, :])))
         out[name] = dict(ms=wall * 1e3, info_max=int(info.max().item()), mean_block_sweeps=float(sw.float().mean().item()),
-                         max_sigma_err=err, prof=prof)
+                         max_sigma_err=err, prof=prof, kern=kern)
     f64 = out["f64"]
     assert f64["info_max"] == 0 and f64["max_sigma_err"] <= 1e-12, f64
     gp = f64["prof"]
-    gram = gp["sketch"]
+    gname = next(k for k in f64["kern"] if k.startswith("bj_gram_kernel<double"))
+    gram = f64["kern"][gname]
     achieved = gram["flops"] / (gram["ms"] * 1e-3) / 1e12
     point_flops = 9.0e9 * b  # point-Jacobi reference: 36 sweeps x 32,640 pairs x 7,680 flops per matrix
     res = dict(value=b / (f64["ms"] * 1e-3), unit="SVDs/s", ms_per_step=f64["ms"], dtype="f64",
@@ -374,8 +377,10 @@ def run_c3(args, torch, P, synth):
                            stage_ms_per_step={k: v["ms"] / args.steps for k, v in gp.items()},
                            point_jacobi_equiv_tflop_per_s=point_flops / (f64["ms"] * 1e-3) / 1e12),
                roofline=dict(bound="mfma", achieved=achieved, peak=FP64_PEAK_TFLOPS, unit="TFLOP/s",
-                             frac=achieved / FP64_PEAK_TFLOPS, traffic=None, kernel="bj_gram_kernel (FP64 MFMA)",
-                             kernel_ms=gram["ms"] / max(1, gram["launches"])))
+                             frac=achieved / FP64_PEAK_TFLOPS, traffic=None, kernel=gname,
+                             kernel_avg_ms=gram["ms"] / max(1, gram["launches"])))
+    res["config"]["kernels"] = [dict(kernel=k, ms_per_step=v["ms"] / args.steps, launches_per_step=v["launches"] / args.steps)
+                                for k, v in sorted(f64["kern"].items(), key=lambda kv: -kv[1]["ms"])[:8]]
     return res
 
 
@@ -389,13 +394,13 @@ def run_c5(args, torch, P, synth):
     import oracle
     from paper_1707_05141_amd import _lib, rankmodel
     count = args.c5_count
-    eps, max_rank, oseed = 1e-6, 64, 777
+    eps, max_rank, oseed = 1e-6, args.c5_max_rank, 777
     # ---- training set and model (untimed)
     t0 = time.perf_counter()
     tm, tn, tk, tw = synth.c5_mixture(6000, seed=501)
     tbuf, toffs = synth.mixed_blocks_packed(tm, tn, tk, tw, seed=501)
     log("training set generated (%.1f s)" % (time.perf_counter() - t0))
-    model = rankmodel.train_packed(tbuf, toffs, tm, tn, eps=eps, seed=11, epochs=60)
+    model = rankmodel.train_packed(tbuf, toffs, tm, tn, eps=eps, seed=11, epochs=60, max_rank=max_rank)
     del tbuf
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
@@ -440,6 +445,9 @@ def run_c5(args, torch, P, synth):
     variants = [("plain_fp64", 0, half, 1), ("mixed", _lib.RSVD_MIXED, half, 1),
                 ("learned_fp64", _lib.RSVD_LEARNED, half, 1),
                 ("learned_mixed", _lib.RSVD_LEARNED | _lib.RSVD_MIXED, args.steps, args.warmup)]
+    if args.c5_variants != "all":
+        keep = set(args.c5_variants.split(",")) | {"plain_fp64", "learned_mixed"}
+        variants = [v for v in variants if v[0] in keep]
     runs = {name: run(name, fl, st, wu) for name, fl, st, wu in variants}
     plain, learned = runs["plain_fp64"], runs["learned_mixed"]
     ok = learned["info"] == 0
@@ -482,7 +490,7 @@ def run_c5(args, torch, P, synth):
     res = dict(value=count / (learned["ms"] * 1e-3), unit="SVDs/s", ms_per_step=learned["ms"], dtype="f32+f64",
                config=dict(workload="rsvd_mixed_learned_100000_blocks_exp_inv_gaussdecay" if count == 100000 else
                            "rsvd_mixed_learned_%d_blocks_exp_inv_gaussdecay" % count,
-                           batch=count, eps=eps, max_rank=max_rank, basis_cap=64,
+                           batch=count, eps=eps, max_rank=max_rank, basis_cap="min(m, n, max_rank + 32)",
                            precision="learned initial sample count + FP32 sketch products; FP64 basis QR, "
                                      "projection, check, rank rule and small SVD",
                            gflop_per_s_model=flops / (learned["ms"] * 1e-3) / 1e9,
@@ -503,7 +511,7 @@ def run_c5(args, torch, P, synth):
 
 def cpu_baseline_c5(buf, offs, m, n, kinds, oseed, eps, max_rank, oracle):
     """The oracle's plain FP64 adaptive randomized SVD on a stratified sample of the same batch (the
-    first 128 instances of each (kind, m, n) class: 6,144 blocks, the exact bytes the GPU factored),
+    first 16 instances of each (kind, m, n) class: 768 blocks, the exact bytes the GPU factored),
     threads across instances; SVDs/s of the sample."""
     from concurrent.futures import ThreadPoolExecutor
     picks = []
@@ -511,7 +519,7 @@ def cpu_baseline_c5(buf, offs, m, n, kinds, oseed, eps, max_rank, oracle):
         for mm in (64, 128, 256, 512):
             for nn in (64, 128, 256, 512):
                 hit = np.nonzero((kinds == kd) & (m == mm) & (n == nn))[0]
-                picks += [int(i) for i in hit[:128]]
+                picks += [int(i) for i in hit[:16]]
     mats = [buf[int(offs[i]):int(offs[i]) + int(m[i]) * int(n[i])].cpu().numpy().reshape(int(n[i]), int(m[i])).T.copy()
             for i in picks]
     threads = os.cpu_count() or 1
@@ -519,14 +527,15 @@ def cpu_baseline_c5(buf, offs, m, n, kinds, oseed, eps, max_rank, oracle):
     def one(j):
         A = mats[j]
         return oracle.rsvd_adaptive(A, seed=oseed, inst=picks[j], eps=eps, blk=8,
-                                    cap=min(A.shape[0], A.shape[1], 64), safety=2.0, max_rank=max_rank)["rank"]
+                                    cap=min(A.shape[0], A.shape[1], max_rank + 32), safety=2.0,
+                                    max_rank=max_rank)["rank"]
 
     t0 = time.perf_counter()
     with ThreadPoolExecutor(max_workers=threads) as ex:
         list(ex.map(one, range(len(picks))))
     dt = time.perf_counter() - t0
     return dict(value=len(picks) / dt, unit="SVDs/s", cores=threads, kind="oracle",
-                sample="%d blocks: the first 128 of each (kind, m, n) class of the same batch, plain FP64 "
+                sample="%d blocks: the first 16 of each (kind, m, n) class of the same batch, plain FP64 "
                        "adaptive finder, %.1f s wall" % (len(picks), dt))
 
 
@@ -542,6 +551,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
     ap.add_argument("--block-w", type=int, default=0, choices=(0, 8, 16, 32), help="0 = autotuned")
     ap.add_argument("--c5-count", type=int, default=100000)
+    ap.add_argument("--c5-max-rank", type=int, default=256)
+    ap.add_argument("--c5-variants", default="all",
+                    help="comma-separated subset of mixed, learned_fp64 to run besides plain_fp64 and learned_mixed")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (y = x * 1, FP64) five times: the reference "
                          "kernel for scaling hardware byte counters")

@@ -177,7 +177,7 @@ int block_jacobi_run(Ctx *c, int dtype, int w, const std::vector<int> &insts, co
                 app_f += tasks_i * 2.0 * (h.M + h.NP) * (double)K * K;
             }
             std::snprintf(tag, sizeof tag, "bj_gram_kernel<%s, %d>", tname, w);
-            pi = c->prof_begin(BSVD_STAGE_SKETCH, tag);
+            pi = c->prof_begin(BSVD_STAGE_JACOBI, tag);
             e = launch_bj_gram(dtype, w, dmats, dt, (int)ntask, tol, c->stream);
             if (e != hipSuccess) return c->hip_fail(e, "block gram launch");
             c->prof_end(pi, gram_b, gram_f);
@@ -191,7 +191,7 @@ int block_jacobi_run(Ctx *c, int dtype, int w, const std::vector<int> &insts, co
             if (e != hipSuccess) return c->hip_fail(e, "block inner svd launch");
             c->prof_end(pi, 0.0, 0.0);
             std::snprintf(tag, sizeof tag, "bj_apply_kernel<%s, %d>", tname, w);
-            pi = c->prof_begin(BSVD_STAGE_OUTPUT, tag);
+            pi = c->prof_begin(BSVD_STAGE_JACOBI, tag);
             e = launch_bj_apply(dtype, w, dmats, dt, (int)ntask, c->stream);
             if (e != hipSuccess) return c->hip_fail(e, "block apply launch");
             c->prof_end(pi, app_b, app_f);

@@ -339,6 +339,7 @@ void bsvd_destroy(bsvd_ctx *ctx) {
     hipSetDevice(c->device);
     hipStreamSynchronize(c->stream);
     if (c->dws) hipFree(c->dws);
+    if (c->dws_aux) hipFree(c->dws_aux);
     if (c->hws) hipHostFree(c->hws);
     if (c->rb) hipHostFree(c->rb);
     if (c->model) hipFree(c->model);

@@ -16,6 +16,10 @@ struct Ctx {
     std::string err;
     void *dws = nullptr;  // device workspace (descriptors, lists, intermediates)
     size_t dws_size = 0;
+    // Second device workspace, swapped in by AuxWorkspace while a nested driver (the block Jacobi
+    // run inside batched_rsvd) lays out its own buffers without touching the caller's.
+    void *dws_aux = nullptr;
+    size_t dws_aux_size = 0;
     void *hws = nullptr;  // pinned host staging for descriptor uploads
     size_t hws_size = 0;
     hipEvent_t staged = nullptr;  // recorded after the last staging upload
@@ -67,6 +71,23 @@ struct Ctx {
     int prof_begin(int stage, const char *tag = nullptr);
     // Close record `idx` with the algorithmic bytes / flops of the launches it brackets.
     void prof_end(int idx, double bytes, double flops);
+};
+
+// While alive, `dws` / `dws_size` refer to the context's auxiliary workspace (and the main one is
+// parked). The staging and readback buffers stay shared: a nested driver may reallocate them, so the
+// outer caller re-reads `hws` / `rb` afterwards.
+struct AuxWorkspace {
+    Ctx *c;
+    explicit AuxWorkspace(Ctx *ctx) : c(ctx) { swap(); }
+    ~AuxWorkspace() { swap(); }
+    void swap() {
+        void *p = c->dws;
+        c->dws = c->dws_aux;
+        c->dws_aux = p;
+        const size_t s = c->dws_size;
+        c->dws_size = c->dws_aux_size;
+        c->dws_aux_size = s;
+    }
 };
 
 }  // namespace bsvd

@@ -75,6 +75,47 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+// Sums of squares that decide ||A||_F^2 - ||B||_F^2 against eps^2 ||A||_F^2 must be accurate far
+// below eps^2 (1e-12 at eps = 1e-6), while a plain FP64 sum of 2.6e5 squares drifts by ~1e-13. They
+// are kept as unevaluated pairs hi + lo with Knuth's error-free TwoSum and the FMA-based exact
+// product error (contraction off, so that every rounding the transformations rely on happens).
+__device__ __forceinline__ void two_sum(double a, double b, double &s, double &e) {
+#pragma clang fp contract(off)
+    s = a + b;
+    const double bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+__device__ __forceinline__ void dd_add_sq(double &hi, double &lo, double x) {
+#pragma clang fp contract(off)
+    const double p = x * x;
+    const double pe = fma(x, x, -p);
+    double s, e;
+    two_sum(hi, p, s, e);
+    hi = s;
+    lo += e + pe;
+}
+__device__ __forceinline__ void dd_add(double &hi, double &lo, double bhi, double blo) {
+#pragma clang fp contract(off)
+    double s, e;
+    two_sum(hi, bhi, s, e);
+    e += lo + blo;
+    hi = s + e;
+    lo = e - (hi - s);
+}
+__device__ __forceinline__ void wave_sum_dd(double &hi, double &lo) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        const double oh = __shfl_xor(hi, o, 64), ol = __shfl_xor(lo, o, 64);
+        dd_add(hi, lo, oh, ol);
+    }
+}
+// Sum of n (hi, lo) pairs stored consecutively, rounded to double.
+__device__ __forceinline__ double dd_sum_pairs(const double *p, int n) {
+    double hi = 0.0, lo = 0.0;
+    for (int i = 0; i < n; ++i) dd_add(hi, lo, p[2 * i], p[2 * i + 1]);
+    return hi + lo;
+}
+
 // ---------------------------------------------------------------------------------------------
 // C (M x N) = alpha X (M x K) Y (K x N) + beta C. X, C column-major; Y column-major (ytrans = 0)
 // or row-major (ytrans = 1, element (k, j) at Y[k * ldy + j]). One 64-lane workgroup per 64-row
@@ -92,7 +133,8 @@ __global__ __launch_bounds__(64) void gemm_nn_kernel(const MMDesc *__restrict__ 
     TA acc[NMAX];
 #pragma unroll
     for (int j = 0; j < NMAX; ++j) acc[j] = TA(0);
-    double xs = 0.0;
+    double xs = 0.0, xl = 0.0;  // sum of the row's squares as hi + lo (only when D.xsq is set)
+    const bool wantx = D.xsq != nullptr;
     const TA *Yp = static_cast<const TA *>(D.Y);
     for (int k0 = 0; k0 < D.K; k0 += KC) {
         const int kc = (D.K - k0) < KC ? (D.K - k0) : KC;
@@ -111,10 +153,12 @@ __global__ __launch_bounds__(64) void gemm_nn_kernel(const MMDesc *__restrict__ 
                 const double x1 = xp[(size_t)(kk + 1) * D.ldx];
                 const double x2 = xp[(size_t)(kk + 2) * D.ldx];
                 const double x3 = xp[(size_t)(kk + 3) * D.ldx];
-                xs = fma(x0, x0, xs);
-                xs = fma(x1, x1, xs);
-                xs = fma(x2, x2, xs);
-                xs = fma(x3, x3, xs);
+                if (wantx) {
+                    dd_add_sq(xs, xl, x0);
+                    dd_add_sq(xs, xl, x1);
+                    dd_add_sq(xs, xl, x2);
+                    dd_add_sq(xs, xl, x3);
+                }
                 const TA y0 = (TA)x0, y1 = (TA)x1, y2 = (TA)x2, y3 = (TA)x3;
 #pragma unroll
                 for (int j = 0; j < NMAX; ++j) {
@@ -126,7 +170,7 @@ __global__ __launch_bounds__(64) void gemm_nn_kernel(const MMDesc *__restrict__ 
             }
             for (; kk < kc; ++kk) {
                 const double x = xp[(size_t)kk * D.ldx];
-                xs = fma(x, x, xs);
+                if (wantx) dd_add_sq(xs, xl, x);
                 const TA y = (TA)x;
 #pragma unroll
                 for (int j = 0; j < NMAX; ++j) acc[j] = fma(y, ys[kk * NMAX + j], acc[j]);
@@ -147,9 +191,12 @@ __global__ __launch_bounds__(64) void gemm_nn_kernel(const MMDesc *__restrict__ 
             }
         }
     }
-    if (D.xsq) {
-        xs = wave_sum(xs);
-        if (lane == 0) D.xsq[tl.y] = xs;
+    if (wantx) {
+        wave_sum_dd(xs, xl);
+        if (lane == 0) {
+            D.xsq[2 * tl.y] = xs;
+            D.xsq[2 * tl.y + 1] = xl;
+        }
     }
     if (D.csq) {
         cs = wave_sum(cs);
@@ -158,7 +205,7 @@ __global__ __launch_bounds__(64) void gemm_nn_kernel(const MMDesc *__restrict__ 
 }
 
 // ---------------------------------------------------------------------------------------------
-// C (K x N) = X^T Y, X column-major M x K, Y column-major M x N, C column-major K x N.
+// C (K x N) = alpha X^T Y + beta C, X column-major M x K, Y column-major M x N, C column-major K x N.
 // One 256-thread workgroup per 64 columns of X. Row chunks of the X tile are loaded coalesced
 // (consecutive lanes read consecutive rows of a column) into LDS transposed, together with the
 // matching rows of Y; lane (c, g) then accumulates column c against output group g (NMAX / 4
@@ -166,11 +213,11 @@ __global__ __launch_bounds__(64) void gemm_nn_kernel(const MMDesc *__restrict__ 
 // ---------------------------------------------------------------------------------------------
 template <int NMAX>
 __global__ __launch_bounds__(256) void gemm_tn_kernel(const MMDesc *__restrict__ d, const int2 *__restrict__ tiles) {
-    constexpr int RC = 32;
+    constexpr int RC = NMAX >= 256 ? 16 : 32;  // rows per chunk (keeps the LDS tiles under 64 KB)
     constexpr int NJ = NMAX / 4;
     __shared__ double xs[RC][65];
     __shared__ double ys[RC][NMAX];
-    __shared__ double red[4];
+    __shared__ double red[8];
     const int2 tl = tiles[blockIdx.x];
     const MMDesc D = d[tl.x];
     const int t = threadIdx.x;
@@ -206,22 +253,34 @@ __global__ __launch_bounds__(256) void gemm_tn_kernel(const MMDesc *__restrict__
         }
         __syncthreads();
     }
-    double cs = 0.0;
+    double cs = 0.0, cl = 0.0;  // sum of the outputs' squares as hi + lo (only when D.csq is set)
     if (cok) {
 #pragma unroll
         for (int j = 0; j < NJ; ++j) {
             const int jj = g * NJ + j;
             if (jj < D.N) {
-                D.C[col + (size_t)jj * D.ldc] = acc[j];
-                cs = fma(acc[j], acc[j], cs);
+                double *cp = D.C + col + (size_t)jj * D.ldc;
+                const double v = D.beta != 0.0 ? fma(D.alpha, acc[j], D.beta * (*cp)) : D.alpha * acc[j];
+                *cp = v;
+                if (D.csq) dd_add_sq(cs, cl, v);
             }
         }
     }
     if (D.csq) {
-        cs = wave_sum(cs);
-        if (c == 0) red[g] = cs;
+        wave_sum_dd(cs, cl);
+        if (c == 0) {
+            red[2 * g] = cs;
+            red[2 * g + 1] = cl;
+        }
         __syncthreads();
-        if (t == 0) D.csq[tl.y] = (red[0] + red[1]) + (red[2] + red[3]);
+        if (t == 0) {
+            double h = red[0], l = red[1];
+            dd_add(h, l, red[2], red[3]);
+            dd_add(h, l, red[4], red[5]);
+            dd_add(h, l, red[6], red[7]);
+            D.csq[2 * tl.y] = h;
+            D.csq[2 * tl.y + 1] = l;
+        }
     }
 }
 
@@ -238,8 +297,7 @@ __global__ void grow_decide_kernel(RsvdState *__restrict__ st, const GrowItem *_
     const GrowItem it = items[t];
     RsvdState &S = st[it.inst];
     if (it.first) {
-        double a = 0.0;
-        for (int i = 0; i < S.ntile_m; ++i) a += S.xsq[i];
+        const double a = dd_sum_pairs(S.xsq, S.ntile_m);
         S.normA2 = a;
         S.nonfinite = __builtin_isfinite(a) ? 0 : 1;
     }
@@ -258,8 +316,7 @@ __global__ void init_norm_kernel(RsvdState *__restrict__ st, const GrowItem *__r
     if (t >= count) return;
     const GrowItem it = items[t];
     RsvdState &S = st[it.inst];
-    double a = 0.0;
-    for (int i = 0; i < S.ntile_m; ++i) a += S.xsq[i];
+    const double a = dd_sum_pairs(S.xsq, S.ntile_m);
     S.normA2 = a;
     S.nonfinite = __builtin_isfinite(a) ? 0 : 1;
     S.ell = it.b;
@@ -271,16 +328,19 @@ __global__ void check_kernel(RsvdState *__restrict__ st, const int *__restrict__
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= count) return;
     RsvdState &S = st[list[t]];
-    double b2 = 0.0;
-    for (int i = 0; i < S.ntile_n; ++i) b2 += S.bsq[i];
+    double b2 = dd_sum_pairs(S.bsq, S.ntile_n);
+    if (S.ell > 256) b2 += dd_sum_pairs(S.bsq2, S.ntile_n);
+    S.normB2 = b2;
     S.check_ok = (S.normA2 - b2) <= S.eps * S.eps * S.normA2 ? 1 : 0;
     S.flag = S.check_ok | S.nonfinite;
     flags[t] = S.flag;
 }
 
 // Truncation (Section 8.2): smallest k with resid2 + sum_{i>=k} sigma_i^2 <= eps^2 ||A||_F^2,
-// resid2 = max(0, ||A||_F^2 - sum_i sigma_i^2), tails summed from the smallest sigma upward; then
-// the outputs S[:k], rank, error estimate and info.
+// tails summed from the smallest sigma upward; then the outputs S[:k], rank, error estimate and
+// info. resid2 = ||A - Q Q^T A||_F^2 = ||A||_F^2 - ||B||_F^2 is taken from the check's accurate sums
+// rather than as ||A||_F^2 - sum_i sigma_i^2: the two agree in exact arithmetic, but the rotations
+// of the SVD of B do not keep ||B||_F to the 1e-14 relative that eps = 1e-6 needs.
 __global__ void finalize_kernel(RsvdState *__restrict__ st, const int *__restrict__ list, int count,
                                 int *__restrict__ rank_out, double *__restrict__ err_out, int *__restrict__ info_out,
                                 const int *__restrict__ jinfo, int *__restrict__ rank_copy, int *__restrict__ ell_out) {
@@ -291,9 +351,7 @@ __global__ void finalize_kernel(RsvdState *__restrict__ st, const int *__restric
     const int ell = S.ell;
     const double *sg = S.sig;
     const double normA2 = S.normA2;
-    double tot = 0.0;
-    for (int i = ell - 1; i >= 0; --i) tot += sg[i] * sg[i];
-    double resid2 = normA2 - tot;
+    double resid2 = normA2 - S.normB2;
     if (resid2 < 0.0) resid2 = 0.0;
     const double thr = S.eps * S.eps * normA2;
     double tail = resid2, tail_at_k = resid2;
@@ -343,9 +401,33 @@ __global__ void ell0_kernel(const float *__restrict__ y, const int *__restrict__
     ell0[t] = e;
 }
 
+// Block updates of the panel orthonormalisation: accumulation of Gram-Schmidt coefficients into R
+// (mode 0, dst += src), zeroing of a block of R below the diagonal (mode 1), copy (mode 2). One
+// workgroup per descriptor.
+__global__ __launch_bounds__(256) void add_block_kernel(const AddDesc *__restrict__ d) {
+    const AddDesc D = d[blockIdx.x];
+    const int tot = D.rows * D.cols;
+    for (int i = threadIdx.x; i < tot; i += 256) {
+        const int c = i / D.rows, r = i - (i / D.rows) * D.rows;
+        double *p = D.dst + r + (size_t)c * D.ldd;
+        if (D.mode == 1)
+            *p = 0.0;
+        else if (D.mode == 2)
+            *p = D.src[r + (size_t)c * D.lds];
+        else
+            *p += D.src[r + (size_t)c * D.lds];
+    }
+}
+
 // ---------------------------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------------------------
+hipError_t launch_add_block(const AddDesc *d, int count, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(add_block_kernel, dim3(count), dim3(256), 0, st, d);
+    return hipGetLastError();
+}
+
 hipError_t launch_ell0(const float *y, const int *cap, int count, float margin, int *ell0, hipStream_t st) {
     if (count <= 0) return hipSuccess;
     hipLaunchKernelGGL(ell0_kernel, dim3((count + 255) / 256), dim3(256), 0, st, y, cap, count, margin, ell0);
@@ -389,6 +471,8 @@ hipError_t launch_gemm_tn(int nmax, const MMDesc *d, const int2 *tiles, int ntil
         case 16: hipLaunchKernelGGL(gemm_tn_kernel<16>, dim3(ntiles), dim3(256), 0, st, d, tiles); break;
         case 32: hipLaunchKernelGGL(gemm_tn_kernel<32>, dim3(ntiles), dim3(256), 0, st, d, tiles); break;
         case 64: hipLaunchKernelGGL(gemm_tn_kernel<64>, dim3(ntiles), dim3(256), 0, st, d, tiles); break;
+        case 128: hipLaunchKernelGGL(gemm_tn_kernel<128>, dim3(ntiles), dim3(256), 0, st, d, tiles); break;
+        case 256: hipLaunchKernelGGL(gemm_tn_kernel<256>, dim3(ntiles), dim3(256), 0, st, d, tiles); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -16,8 +16,9 @@ struct MMDesc {
     const double *X;
     const void *Y;  // double, or float for the FP32 sketch kernel
     double *C;
-    double *xsq;  // nullable: per-tile partial sums of X^2 (gemm_nn only)
-    double *csq;  // nullable: per-tile partial sums of the outputs' squares
+    double *xsq;  // nullable: per-tile partial sums of X^2 as (hi, lo) pairs (gemm_nn only)
+    double *csq;  // nullable: per-tile partial sums of the outputs' squares: one double per tile
+                  // in gemm_nn, a (hi, lo) pair per tile in gemm_tn
     double alpha, beta;
     int M, N, K, ldx, ldy, ldc, ytrans;
 };
@@ -25,10 +26,12 @@ struct MMDesc {
 // Device-resident state of one randomized-SVD instance.
 struct RsvdState {
     const double *A;
-    double *xsq, *csq, *bsq;  // per-tile partial sums (row tiles of A, row tiles of A, column tiles of A)
+    double *xsq, *csq, *bsq;  // per-tile partial sums: ||A||^2 over row tiles (hi, lo pairs), the
+                              // estimator over row tiles, ||B||^2 over column tiles of A (pairs)
+    double *bsq2;             // ||B||^2 pairs of basis columns 256 and up (ell > 256), else unused
     double *sig;              // singular values of R_B^T (capacity cap)
     double *Sout;             // caller's S
-    double normA2, eps, safety;
+    double normA2, normB2, eps, safety;
     int m, n, lda, cap, ell, max_rank;
     int ntile_m, ntile_n;
     int flag, check_ok, nonfinite, rank;
@@ -39,6 +42,14 @@ struct GrowItem {
     int inst, b, first, pad;
 };
 
+// Block operation on dst (rows x cols, ld ldd): mode 0 dst += src, 1 dst = 0, 2 dst = src
+struct AddDesc {
+    const double *src;
+    double *dst;
+    int rows, cols, lds, ldd, mode;
+};
+
+hipError_t launch_add_block(const AddDesc *d, int count, hipStream_t st);
 hipError_t launch_rng(const RngDesc *d, const int2 *tiles, int ntiles, unsigned long long seed, hipStream_t st);
 hipError_t launch_gemm_nn(int nmax, const MMDesc *d, const int2 *tiles, int ntiles, hipStream_t st);
 // FP32 arithmetic variant of gemm_nn (X rounded to FP32, Y FP32, FP32 accumulation, C stored FP64).

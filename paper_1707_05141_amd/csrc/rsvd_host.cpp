@@ -9,16 +9,29 @@
 //
 // Per instance (all FP64, column-major, in the context's workspace):
 //   Q   m x cap   orthonormal basis of the sampled range, grown block by block
-//   Y   m x cap   current sample block Y = A Omega, then its projection
+//   Y   max(m, n) x cap  current sample block Y = A Omega and its projections; once the basis is
+//                 complete the same storage holds B^T = A^T Q (n x ell)
 //   Om  n x bmax  Gaussian block, row-major
-//   H   cap x 8   Q^T Y for the two classical Gram-Schmidt passes
-//   Bt  n x cap   B^T = A^T Q
+//   H   cap x 64  projection coefficients Q^T Y of the classical Gram-Schmidt passes
 //   QB  n x cap, RB cap x cap  QR of B^T
-//   UR, VR cap x cap, sig cap  SVD of R_B^T by one-sided Jacobi (rotating the rows of R_B)
-// with cap = min(m, n, 64).
+//   UR, VR cap x cap, sig cap  SVD of R_B^T
+// with cap = min(m, n, max_rank + 32).
+//
+// Up to 64 columns a matrix is factored by the one-kernel Householder QR, and R_B^T by the
+// wavefront- or LDS-resident Jacobi kernels. Wider bases (ell > 64) are built panel by panel
+// (64 columns): each panel is projected out of the previous ones twice (block classical
+// Gram-Schmidt with reorthogonalisation) and then factored by the Householder kernel; the
+// coefficients of both passes form R. R_B is then diagonalised by the block Jacobi method in HBM
+// (Algorithm 3), rotating its columns: R_B = V_R S U_R^T, so its left vectors are V_R and its
+// right vectors U_R.
+//
+// A batch whose workspace would exceed the budget is processed in consecutive sub-batches; the
+// Gaussian draws are indexed by the instance's position in the whole batch, so the result does not
+// depend on the split.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <vector>
@@ -34,17 +47,32 @@ using namespace bsvd;
 
 namespace {
 
-constexpr int CAPMAX = 64;
+constexpr int CAPMAX = 512;
+constexpr int CAP_OVER = 32;  // basis columns allowed beyond max_rank
+constexpr int PANEL = 64;     // widest matrix of the one-kernel QR / small Jacobi paths
 constexpr int GROW_BLK = 8;
+constexpr int BLOCK_W = 16;   // block width of the block Jacobi on R_B for ell > PANEL
 constexpr double SAFETY = 2.0;
+constexpr size_t WS_BUDGET = (size_t)24 << 30;  // workspace bound of one sub-batch
 
+// NMAX class of the lane-per-row GEMM (N <= 64) and of the X^T Y GEMM (N <= 256)
 inline int nmax_for(int x) { return x <= 8 ? 8 : (x <= 16 ? 16 : (x <= 32 ? 32 : 64)); }
+inline int nmax_tn(int x) { return x <= 64 ? nmax_for(x) : (x <= 128 ? 128 : 256); }
 inline int cdiv(int a, int b) { return (a + b - 1) / b; }
 
 struct Inst {
     int m, n, lda, cap, ell, ell0, maxr;
-    size_t oQ, oY, oOm, oH, oBt, oQB, oRB, oUR, oVR, oSig, oXsq, oCsq, oBsq;
+    size_t oQ, oY, oOm, oH, oT, oQB, oRB, oUR, oVR, oSig, oXsq, oCsq, oBsq, oBsq2;
 };
+
+// Workspace bytes of one instance (see the layout above), rounded as the arena rounds.
+inline size_t inst_bytes(int m, int n, int cap, int bmax) {
+    auto r = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t M = m, N = n, C = cap;
+    return r(8 * M * C) + r(8 * std::max(M, N) * C) + r(8 * N * bmax) + r(8 * C * PANEL) +
+           r(cap > PANEL ? 8 * 2 * PANEL * PANEL : 8) + r(8 * N * C) +
+           3 * r(8 * C * C) + r(8 * C) + r(16 * (size_t)cdiv(m, 64)) * 2 + r(16 * (size_t)cdiv(n, 64)) * 2;
+}
 
 // Sequential packer of one round's descriptors into the pinned staging buffer; device addresses
 // are those the block will have after upload_to(doff).
@@ -93,7 +121,8 @@ struct ProbeBufs {
 };
 
 static int probe_features(Ctx *c, int batch, const int *m, const int *n, const void *const *A, const int *lda,
-                          const std::vector<ProbeBufs> &pb, unsigned long long seed, float *feats, size_t desc_cap) {
+                          const std::vector<ProbeBufs> &pb, unsigned long long seed, float *feats, size_t desc_cap,
+                          int inst_base) {
     Packer p;
     int rc = c->ensure_host(desc_cap);
     if (rc) return rc;
@@ -112,7 +141,7 @@ static int probe_features(Ctx *c, int batch, const int *m, const int *n, const v
     std::map<int, std::pair<double, double>> skcost;  // per NMAX: algorithmic bytes, flops
     for (int b = 0; b < batch; ++b) {
         const int kp = std::min(PROBE_COLS, std::min(m[b], n[b]));
-        hrd[b] = RngDesc{pb[b].Om, n[b], kp, PROBE_COL0, kp, b, 0};
+        hrd[b] = RngDesc{pb[b].Om, n[b], kp, PROBE_COL0, kp, inst_base + b, 0};
         for (int t = 0; t < cdiv(n[b] * kp, 256); ++t) rt.push_back(make_int2(b, t));
         MMDesc d;
         d.X = static_cast<const double *>(A[b]); d.Y = pb[b].Om; d.C = pb[b].Y; d.xsq = nullptr; d.csq = nullptr;
@@ -224,60 +253,36 @@ extern "C" int bsvd_rank_features(bsvd_ctx *ctx, int batch, const int *m, const 
     for (int b = 0; b < batch; ++b)
         pb[b] = ProbeBufs{reinterpret_cast<double *>(db + o[3 * b]), reinterpret_cast<double *>(db + o[3 * b + 1]),
                           reinterpret_cast<double *>(db + o[3 * b + 2]), PROBE_COLS};
-    return probe_features(c, batch, m, n, A, lda, pb, seed, feats, dsz);
+    return probe_features(c, batch, m, n, A, lda, pb, seed, feats, dsz, 0);
 }
 
-extern "C" int batched_rsvd(bsvd_ctx *ctx, int batch, const int *m, const int *n, const void *const *A,
-                            const int *lda, const double *eps, const int *max_rank, void *const *S, void *const *U,
-                            const int *ldu, void *const *V, const int *ldv, int *rank, double *err_est, int *info,
-                            unsigned long long seed, unsigned flags, const int *ell0, int *samples) {
-    if (!ctx) return BSVD_EARG;
-    Ctx *c = reinterpret_cast<Ctx *>(ctx);
-    c->err.clear();
-    if (batch < 0) return c->fail(BSVD_EARG, "batch = %d < 0", batch);
-    if (batch == 0) return BSVD_OK;
-    if (!m || !n || !A || !lda || !max_rank || !S) return c->fail(BSVD_EARG, "m, n, A, lda, max_rank and S must be non-NULL");
-    if (U && !ldu) return c->fail(BSVD_EARG, "U given without ldu");
-    if (V && !ldv) return c->fail(BSVD_EARG, "V given without ldv");
-    if ((flags & BSVD_RSVD_FIXED) && !ell0) return c->fail(BSVD_EARG, "BSVD_RSVD_FIXED needs ell0");
-    if ((flags & BSVD_RSVD_LEARNED) && (ell0 || (flags & BSVD_RSVD_FIXED)))
-        return c->fail(BSVD_EARG, "BSVD_RSVD_LEARNED chooses ell0 itself (pass ell0 = NULL, no FIXED)");
-    if ((flags & BSVD_RSVD_LEARNED) && !c->model) return c->fail(BSVD_EARG, "BSVD_RSVD_LEARNED needs a rank model");
-    if (flags & ~(unsigned)(BSVD_RSVD_FIXED | BSVD_RSVD_LEARNED | BSVD_RSVD_MIXED))
-        return c->fail(BSVD_EUNSUP, "flags 0x%x not supported", flags);
+// One sub-batch: instances [0, batch) of the arrays given, which are instances inst_base ... of the
+// caller's batch (the Gaussian draws use the caller's index).
+static int rsvd_range(Ctx *c, int inst_base, int batch, const int *m, const int *n, const void *const *A,
+                      const int *lda, const double *eps, const int *max_rank, void *const *S, void *const *U,
+                      const int *ldu, void *const *V, const int *ldv, int *rank, double *err_est, int *info,
+                      unsigned long long seed, unsigned flags, const int *ell0, int *samples) {
     const bool learned = (flags & BSVD_RSVD_LEARNED) != 0;
     const bool mixed = (flags & BSVD_RSVD_MIXED) != 0;
-    hipError_t e = hipSetDevice(c->device);
-    if (e != hipSuccess) return c->hip_fail(e, "hipSetDevice");
+    hipError_t e;
 
-    // ---- validation and workspace layout ---------------------------------------------------
+    // ---- workspace layout -------------------------------------------------------------------
     std::vector<Inst> I(batch);
     size_t dsz = 1u << 16;  // descriptor region bound
     for (int b = 0; b < batch; ++b) {
-        if (m[b] < 1) return c->fail(BSVD_EARG, "instance %d: m = %d < 1", b, m[b]);
-        if (n[b] < 1) return c->fail(BSVD_EARG, "instance %d: n = %d < 1", b, n[b]);
-        if (m[b] > 512 || n[b] > 512)
-            return c->fail(BSVD_EUNSUP, "instance %d: %d x %d exceeds the 512 x 512 limit", b, m[b], n[b]);
-        if (lda[b] < m[b]) return c->fail(BSVD_EARG, "instance %d: lda = %d < m = %d", b, lda[b], m[b]);
-        if (!A[b]) return c->fail(BSVD_EARG, "instance %d: A is NULL", b);
-        if (!S[b]) return c->fail(BSVD_EARG, "instance %d: S is NULL", b);
-        if (max_rank[b] < 1) return c->fail(BSVD_EARG, "instance %d: max_rank = %d < 1", b, max_rank[b]);
-        if (U && U[b] && ldu[b] < m[b]) return c->fail(BSVD_EARG, "instance %d: ldu = %d < m = %d", b, ldu[b], m[b]);
-        if (V && V[b] && ldv[b] < n[b]) return c->fail(BSVD_EARG, "instance %d: ldv = %d < n = %d", b, ldv[b], n[b]);
-        if (eps && !(eps[b] > 0.0 && eps[b] < 1.0))
-            return c->fail(BSVD_EARG, "instance %d: eps = %g not in (0, 1)", b, eps[b]);
         Inst &q = I[b];
         q.m = m[b];
         q.n = n[b];
         q.lda = lda[b];
-        q.cap = std::min(std::min(m[b], n[b]), CAPMAX);
+        q.cap = std::min(std::min(std::min(m[b], n[b]), CAPMAX), max_rank[b] + CAP_OVER);
         q.ell = 0;
         q.ell0 = ell0 ? std::min(std::max(ell0[b], 0), q.cap) : 0;
-        if ((flags & BSVD_RSVD_FIXED) && q.ell0 < 1) return c->fail(BSVD_EARG, "instance %d: ell0 < 1 with FIXED", b);
         q.maxr = max_rank[b];
         if (learned) q.ell0 = q.cap;  // the learned count is at most cap: size buffers for it
         const int bmax = std::max(std::max(GROW_BLK, q.ell0), PROBE_COLS);
-        dsz += 4096 + 8 * (size_t)cdiv(q.n * bmax, 256) + 96 * (size_t)cdiv(q.m, 64) + 96 * (size_t)cdiv(q.n, 64);
+        const int pan = cdiv(q.cap, PANEL);
+        dsz += 4096 + 8 * (size_t)cdiv(q.n * bmax, 256) + (96 * pan + 192) * (size_t)cdiv(std::max(q.m, q.n), 64) +
+               64 * (size_t)cdiv(q.cap, 64) * pan + 512 * (size_t)pan;
     }
     dsz = (dsz + 4095) & ~(size_t)4095;
     Arena ar;
@@ -295,18 +300,19 @@ extern "C" int batched_rsvd(bsvd_ctx *ctx, int batch, const int *m, const int *n
         const size_t M = q.m, N = q.n, C = q.cap;
         const size_t bmax = std::max(std::max(GROW_BLK, q.ell0), PROBE_COLS);
         q.oQ = ar.alloc(8 * M * C);
-        q.oY = ar.alloc(8 * M * C);
+        q.oY = ar.alloc(8 * std::max(M, N) * C);
         q.oOm = ar.alloc(8 * N * bmax);
-        q.oH = ar.alloc(8 * C * GROW_BLK);
-        q.oBt = ar.alloc(8 * N * C);
+        q.oH = ar.alloc(8 * C * PANEL);
+        q.oT = ar.alloc(q.cap > PANEL ? 8 * 2 * PANEL * PANEL : 8);
         q.oQB = ar.alloc(8 * N * C);
         q.oRB = ar.alloc(8 * C * C);
         q.oUR = ar.alloc(8 * C * C);
         q.oVR = ar.alloc(8 * C * C);
         q.oSig = ar.alloc(8 * C);
-        q.oXsq = ar.alloc(8 * (size_t)cdiv(q.m, 64));
+        q.oXsq = ar.alloc(16 * (size_t)cdiv(q.m, 64));
         q.oCsq = ar.alloc(8 * (size_t)cdiv(q.m, 64));
-        q.oBsq = ar.alloc(8 * (size_t)cdiv(q.n, 64));
+        q.oBsq = ar.alloc(16 * (size_t)cdiv(q.n, 64));
+        q.oBsq2 = ar.alloc(16 * (size_t)cdiv(q.n, 64));
     }
     int rc = c->ensure_device(ar.off);
     if (rc) return rc;
@@ -320,7 +326,7 @@ extern "C" int batched_rsvd(bsvd_ctx *ctx, int batch, const int *m, const int *n
     int *djsweeps = reinterpret_cast<int *>(db + oJsweeps);
     int *dflags = reinterpret_cast<int *>(db + oFlags);
     int *drankc = reinterpret_cast<int *>(db + oRankc);
-    const int *rb = static_cast<const int *>(c->rb);
+    auto rbv = [&]() { return static_cast<const int *>(c->rb); };
 
     {
         RsvdState *hs = static_cast<RsvdState *>(c->hws);
@@ -332,6 +338,7 @@ extern "C" int batched_rsvd(bsvd_ctx *ctx, int batch, const int *m, const int *n
             s.xsq = reinterpret_cast<double *>(db + q.oXsq);
             s.csq = reinterpret_cast<double *>(db + q.oCsq);
             s.bsq = reinterpret_cast<double *>(db + q.oBsq);
+            s.bsq2 = reinterpret_cast<double *>(db + q.oBsq2);
             s.sig = reinterpret_cast<double *>(db + q.oSig);
             s.Sout = static_cast<double *>(S[b]);
             s.eps = eps ? eps[b] : 1e-6;
@@ -370,7 +377,7 @@ extern "C" int batched_rsvd(bsvd_ctx *ctx, int batch, const int *m, const int *n
         if (ee != hipSuccess) return c->hip_fail(ee, "hipStreamSynchronize");
         return BSVD_OK;
     };
-    // Pack a set of GEMM descriptors grouped by NMAX together with their tile lists and launch them.
+    // GEMM descriptors grouped by NMAX, packed with their tile lists, launched one per group.
     struct Pending {
         int nmax;
         int tn;  // 0 nn, 1 tn, 2 nn with FP32 arithmetic
@@ -398,10 +405,11 @@ extern "C" int batched_rsvd(bsvd_ctx *ctx, int batch, const int *m, const int *n
                 for (int t = 0; t < g.tiles_per[i]; ++t) ht[k++] = make_int2((int)i, t);
                 const double M = md.M, N = md.N, K = md.K;
                 fl += 2.0 * M * N * K;
-                if (tn == 1)  // C (K x N) = X^T Y
-                    by += 8.0 * (M * K + M * N + K * N);
+                const double cio = md.beta != 0.0 ? 2.0 : 1.0;
+                if (tn == 1)  // C (K x N) = alpha X^T Y + beta C
+                    by += 8.0 * (M * K + M * N + K * N * cio);
                 else  // C (M x N) = alpha X Y + beta C; the FP32 variant reads Y as FP32
-                    by += 8.0 * M * K + (tn == 2 ? 4.0 : 8.0) * K * N + 8.0 * M * N * (md.beta != 0.0 ? 2.0 : 1.0);
+                    by += 8.0 * M * K + (tn == 2 ? 4.0 : 8.0) * K * N + 8.0 * M * N * cio;
             }
             out.push_back(Pending{kv.first, tn, dd, dt, nt, by, fl});
         }
@@ -417,12 +425,33 @@ extern "C" int batched_rsvd(bsvd_ctx *ctx, int batch, const int *m, const int *n
         }
         return BSVD_OK;
     };
-    auto mm_nn = [&](const double *X, int ldx, const double *Y, int ldy, int ytrans, double *C, int ldc, int M,
-                     int N, int K, double alpha, double beta, double *xsq, double *csq) {
+    auto mmd = [&](const double *X, int ldx, const void *Y, int ldy, int ytrans, double *C, int ldc, int M, int N,
+                   int K, double alpha, double beta, double *xsq, double *csq) {
         MMDesc d;
         d.X = X; d.Y = Y; d.C = C; d.xsq = xsq; d.csq = csq; d.alpha = alpha; d.beta = beta;
         d.M = M; d.N = N; d.K = K; d.ldx = ldx; d.ldy = ldy; d.ldc = ldc; d.ytrans = ytrans;
         return d;
+    };
+    // C (M x N) = alpha X Y + beta C through the lane-per-row kernel, split into 64-column pieces
+    // (each piece reads X again); ysz is the element size of Y. Only the first piece carries xsq, and
+    // csq is allowed only for a single piece.
+    auto add_nn = [&](std::map<int, MMGroup> &g, const MMDesc &d0, size_t ysz) {
+        for (int c0 = 0; c0 < d0.N; c0 += PANEL) {
+            MMDesc d = d0;
+            d.N = std::min(PANEL, d0.N - c0);
+            d.Y = static_cast<const char *>(d0.Y) + ysz * (d0.ytrans ? (size_t)c0 : (size_t)c0 * d0.ldy);
+            d.C = d0.C + (size_t)c0 * d0.ldc;
+            if (c0 > 0) d.xsq = nullptr;
+            MMGroup &gg = g[nmax_for(d.N)];
+            gg.desc.push_back(d);
+            gg.tiles_per.push_back(cdiv(d.M, 64));
+        }
+    };
+    // C (K x N) = alpha X^T Y + beta C through the column-tile kernel (N <= 256)
+    auto add_tn = [&](std::map<int, MMGroup> &g, const MMDesc &d) {
+        MMGroup &gg = g[nmax_tn(d.N)];
+        gg.desc.push_back(d);
+        gg.tiles_per.push_back(cdiv(d.K, 64));
     };
     // QR launches grouped by kernel configuration, with their algorithmic cost: Householder
     // factorisation and formation of the thin Q (2 (2 m n^2 - 2 n^3 / 3) flops); A read, Q written,
@@ -462,6 +491,116 @@ extern "C" int batched_rsvd(bsvd_ctx *ctx, int batch, const int *m, const int *n
         }
         return BSVD_OK;
     };
+    auto qrdesc = [&](double *Ain, int mm, int nn, int ldA, double *Q, int ldq, double *R, int ldr) {
+        QrDesc qd;
+        qd.A = Ain; qd.m = mm; qd.n = nn; qd.lda = ldA; qd.trans = 0;
+        qd.Q = Q; qd.ldq = ldq; qd.R = R; qd.ldr = ldr;
+        return qd;
+    };
+
+    // Orthonormalisation of a matrix X (rows x cols, ld = rows) that is wider than one panel: panel 0
+    // by the Householder kernel; panel j > 0 (P, columns c0 = 64 j ...) by
+    //   1-2. two classical Gram-Schmidt passes against Qo[:, :c0] (coefficients C1 + C2),
+    //   3.   Householder QR of the residual: P = Qp Rp,
+    //   4.   one more pass on the normalised Qp (D = Qo^T Qp, Qp -= Qo D) and its QR: Qp = Qp' R'.
+    // Step 4 keeps the panel orthogonal to the previous ones when the residual of steps 1-2 is at
+    // rounding level (a panel that is numerically inside span(Qo), e.g. more samples than the
+    // numerical rank): there the normalised Qp can lean on Qo by O(1), and the third pass, working
+    // on vectors of norm one, removes that exactly. Then X = Qo R with, for the panel,
+    //   R[0:c0, panel] = C1 + C2 + D Rp,   R[panel, panel] = R' Rp,   R[panel, 0:c0] = 0.
+    // Writes Qo (rows x cols) and, when R is given, R (cols x cols, ld ldr); X is overwritten; T1,
+    // T2 (64 x 64 each) hold Rp and R'. One round per panel index, batched over the jobs.
+    struct PanelJob {
+        int inst, rows, cols;
+        double *X, *Qo, *R, *H, *T1, *T2;
+        int ldr, ldh;
+    };
+    auto panel_qr = [&](const std::vector<PanelJob> &jobs) -> int {
+        int maxp = 0;
+        for (const PanelJob &j : jobs) maxp = std::max(maxp, cdiv(j.cols, PANEL));
+        for (int pj = 0; pj < maxp; ++pj) {
+            Packer p;
+            int r2 = new_packer(p);
+            if (r2) return r2;
+            std::map<int, MMGroup> t1, n1, t2, n2, t3, n3, nr1, nr2;
+            std::vector<QrDesc> qv1, qv2;
+            std::vector<AddDesc> adds, copies;
+            for (const PanelJob &j : jobs) {
+                const int c0 = pj * PANEL;
+                if (c0 >= j.cols) continue;
+                const int pw = std::min(PANEL, j.cols - c0);
+                double *P = j.X + (size_t)c0 * j.rows;
+                double *Qp = j.Qo + (size_t)c0 * j.rows;
+                if (pj == 0) {
+                    qv1.push_back(qrdesc(P, j.rows, pw, j.rows, Qp, j.rows, j.R, j.ldr));
+                    continue;
+                }
+                double *C1 = j.R ? j.R + (size_t)c0 * j.ldr : j.H;
+                const int ld1 = j.R ? j.ldr : j.ldh;
+                add_tn(t1, mmd(j.Qo, j.rows, P, j.rows, 0, C1, ld1, j.rows, pw, c0, 1.0, 0.0, nullptr, nullptr));
+                add_nn(n1, mmd(j.Qo, j.rows, C1, ld1, 0, P, j.rows, j.rows, pw, c0, -1.0, 1.0, nullptr, nullptr), 8);
+                add_tn(t2, mmd(j.Qo, j.rows, P, j.rows, 0, j.H, j.ldh, j.rows, pw, c0, 1.0, 0.0, nullptr, nullptr));
+                add_nn(n2, mmd(j.Qo, j.rows, j.H, j.ldh, 0, P, j.rows, j.rows, pw, c0, -1.0, 1.0, nullptr, nullptr), 8);
+                if (j.R) {
+                    adds.push_back(AddDesc{j.H, j.R + (size_t)c0 * j.ldr, c0, pw, j.ldh, j.ldr, 0});
+                    adds.push_back(AddDesc{nullptr, j.R + c0, pw, c0, 0, j.ldr, 1});  // R[panel, 0:c0] = 0
+                }
+                qv1.push_back(qrdesc(P, j.rows, pw, j.rows, Qp, j.rows, j.R ? j.T1 : nullptr, PANEL));
+                // step 4: D = Qo^T Qp into H, P := Qp - Qo D, Qp' R' = qr(P)
+                add_tn(t3, mmd(j.Qo, j.rows, Qp, j.rows, 0, j.H, j.ldh, j.rows, pw, c0, 1.0, 0.0, nullptr, nullptr));
+                copies.push_back(AddDesc{Qp, P, j.rows, pw, j.rows, j.rows, 2});
+                add_nn(n3, mmd(j.Qo, j.rows, j.H, j.ldh, 0, P, j.rows, j.rows, pw, c0, -1.0, 1.0, nullptr, nullptr), 8);
+                qv2.push_back(qrdesc(P, j.rows, pw, j.rows, Qp, j.rows, j.R ? j.T2 : nullptr, PANEL));
+                if (j.R) {
+                    add_nn(nr1, mmd(j.H, j.ldh, j.T1, PANEL, 0, j.R + (size_t)c0 * j.ldr, j.ldr, c0, pw, pw, 1.0, 1.0,
+                                    nullptr, nullptr),
+                           8);
+                    add_nn(nr2, mmd(j.T2, PANEL, j.T1, PANEL, 0, j.R + c0 + (size_t)c0 * j.ldr, j.ldr, pw, pw, pw, 1.0,
+                                    0.0, nullptr, nullptr),
+                           8);
+                }
+            }
+            std::vector<Pending> m1, m2, m3, m4, m5, m6, m7, m8;
+            pack_mm(p, t1, 1, m1);
+            pack_mm(p, n1, 0, m2);
+            pack_mm(p, t2, 1, m3);
+            pack_mm(p, n2, 0, m4);
+            pack_mm(p, t3, 1, m5);
+            pack_mm(p, n3, 0, m6);
+            pack_mm(p, nr1, 0, m7);
+            pack_mm(p, nr2, 0, m8);
+            AddDesc *dad = nullptr, *dcp = nullptr;
+            if (!adds.empty()) {
+                AddDesc *had = p.put<AddDesc>(adds.size(), &dad);
+                if (had) std::copy(adds.begin(), adds.end(), had);
+            }
+            if (!copies.empty()) {
+                AddDesc *hcp = p.put<AddDesc>(copies.size(), &dcp);
+                if (hcp) std::copy(copies.begin(), copies.end(), hcp);
+            }
+            QrDesc *dq1, *dq2 = nullptr;
+            std::vector<QLaunch> ql1, ql2;
+            if ((r2 = pack_qr(p, qv1, ql1, &dq1))) return c->fail(r2, "internal: no QR kernel for a panel");
+            if (!qv2.empty() && (r2 = pack_qr(p, qv2, ql2, &dq2))) return c->fail(r2, "internal: no QR kernel for a panel");
+            if ((r2 = commit(p))) return r2;
+            auto run_add = [&](AddDesc *dd, size_t cnt) -> int {
+                if (!cnt) return BSVD_OK;
+                const int pi = c->prof_begin(BSVD_STAGE_CGS, "add_block_kernel");
+                hipError_t ee = launch_add_block(dd, (int)cnt, c->stream);
+                if (ee != hipSuccess) return c->hip_fail(ee, "add launch");
+                c->prof_end(pi, 0.0, 0.0);
+                return BSVD_OK;
+            };
+            if ((r2 = launch_mm(m1, BSVD_STAGE_CGS)) || (r2 = launch_mm(m2, BSVD_STAGE_CGS)) ||
+                (r2 = launch_mm(m3, BSVD_STAGE_CGS)) || (r2 = launch_mm(m4, BSVD_STAGE_CGS)) ||
+                (r2 = run_add(dad, adds.size())) || (r2 = launch_qrs(dq1, ql1)) ||
+                (r2 = launch_mm(m5, BSVD_STAGE_CGS)) || (r2 = run_add(dcp, copies.size())) ||
+                (r2 = launch_mm(m6, BSVD_STAGE_CGS)) || (!ql2.empty() && (r2 = launch_qrs(dq2, ql2))) ||
+                (r2 = launch_mm(m7, BSVD_STAGE_CGS)) || (r2 = launch_mm(m8, BSVD_STAGE_CGS)))
+                return r2;
+        }
+        return BSVD_OK;
+    };
 
     // ---- learned initial sample count: probe features -> network -> ell0 ----------------------
     if (learned) {
@@ -470,7 +609,7 @@ extern "C" int batched_rsvd(bsvd_ctx *ctx, int batch, const int *m, const int *n
         float *dfeat = reinterpret_cast<float *>(db + oFeat);
         float *dpred = reinterpret_cast<float *>(db + oPred);
         int *dcap = reinterpret_cast<int *>(db + oCap);
-        if ((rc = probe_features(c, batch, m, n, A, lda, pb, seed, dfeat, dsz))) return rc;
+        if ((rc = probe_features(c, batch, m, n, A, lda, pb, seed, dfeat, dsz, inst_base))) return rc;
         if ((rc = c->ensure_host(dsz))) return rc;
         int *hc = static_cast<int *>(c->hws);
         for (int b = 0; b < batch; ++b) hc[b] = I[b].cap;
@@ -482,7 +621,7 @@ extern "C" int batched_rsvd(bsvd_ctx *ctx, int batch, const int *m, const int *n
         if (e != hipSuccess) return c->hip_fail(e, "ell0 launch");
         c->prof_end(pi, 0.0, 0.0);
         if ((rc = readback(batch))) return rc;
-        for (int b = 0; b < batch; ++b) I[b].ell0 = rb[b];
+        for (int b = 0; b < batch; ++b) I[b].ell0 = rbv()[b];
     }
 
     // ---- phase A: initial block of ell0 samples (Algorithm 4 as printed) -------------------
@@ -501,24 +640,25 @@ extern "C" int batched_rsvd(bsvd_ctx *ctx, int batch, const int *m, const int *n
             GrowItem *dgi;
             GrowItem *hgi = p.put<GrowItem>(init.size(), &dgi);
             if (!hrd || !hgi) return commit(p);
+            std::vector<PanelJob> wide;
+            double rgb = 0;
             for (size_t i = 0; i < init.size(); ++i) {
                 const int b = init[i];
                 Inst &q = I[b];
-                hrd[i] = RngDesc{dptr(q.oOm), q.n, q.ell0, 0, q.ell0, b, mixed ? 1 : 0};
+                hrd[i] = RngDesc{dptr(q.oOm), q.n, q.ell0, 0, q.ell0, inst_base + b, mixed ? 1 : 0};
+                rgb += (mixed ? 4.0 : 8.0) * q.n * (double)q.ell0;
                 for (int t = 0; t < cdiv(q.n * q.ell0, 256); ++t) rt.push_back(make_int2((int)i, t));
-                MMGroup &g = sk[nmax_for(q.ell0)];
-                g.desc.push_back(mm_nn(static_cast<const double *>(A[b]), q.lda, dptr(q.oOm), q.ell0, 1, dptr(q.oY),
-                                       q.m, q.m, q.ell0, q.n, 1.0, 0.0, dptr(q.oXsq), nullptr));
-                g.tiles_per.push_back(cdiv(q.m, 64));
-                QrDesc qd;
-                qd.A = dptr(q.oY); qd.m = q.m; qd.n = q.ell0; qd.lda = q.m; qd.trans = 0;
-                qd.Q = dptr(q.oQ); qd.ldq = q.m; qd.R = nullptr; qd.ldr = 0;
-                qv.push_back(qd);
+                add_nn(sk, mmd(static_cast<const double *>(A[b]), q.lda, dptr(q.oOm), q.ell0, 1, dptr(q.oY), q.m, q.m,
+                               q.ell0, q.n, 1.0, 0.0, dptr(q.oXsq), nullptr),
+                       mixed ? 4 : 8);
+                if (q.ell0 <= PANEL)
+                    qv.push_back(qrdesc(dptr(q.oY), q.m, q.ell0, q.m, dptr(q.oQ), q.m, nullptr, 0));
+                else
+                    wide.push_back(PanelJob{b, q.m, q.ell0, dptr(q.oY), dptr(q.oQ), nullptr, dptr(q.oH), nullptr,
+                                            nullptr, 0, q.cap});
                 hgi[i] = GrowItem{b, q.ell0, 1, 0};
                 q.ell = q.ell0;
             }
-            double rgb = 0;
-            for (int b : init) rgb += (mixed ? 4.0 : 8.0) * I[b].n * (double)I[b].ell0;
             int2 *drt;
             int2 *hrt = p.put<int2>(rt.size(), &drt);
             if (hrt) std::copy(rt.begin(), rt.end(), hrt);
@@ -538,6 +678,7 @@ extern "C" int batched_rsvd(bsvd_ctx *ctx, int batch, const int *m, const int *n
             e = launch_init_norm(dstate, dgi, (int)init.size(), c->stream);
             if (e != hipSuccess) return c->hip_fail(e, "init launch");
             c->prof_end(pi, 0.0, 0.0);
+            if (!wide.empty() && (rc = panel_qr(wide))) return rc;
             pend_check = init;
         }
     }
@@ -563,30 +704,24 @@ extern "C" int batched_rsvd(bsvd_ctx *ctx, int batch, const int *m, const int *n
                 const int blk = std::min(GROW_BLK, q.cap - q.ell);
                 const int first = q.ell == 0;
                 rgb += (mixed ? 4.0 : 8.0) * q.n * (double)blk;
-                hrd[i] = RngDesc{dptr(q.oOm), q.n, blk, q.ell, blk, b, mixed ? 1 : 0};
+                hrd[i] = RngDesc{dptr(q.oOm), q.n, blk, q.ell, blk, inst_base + b, mixed ? 1 : 0};
                 for (int t = 0; t < cdiv(q.n * blk, 256); ++t) rt.push_back(make_int2(i, t));
-                MMGroup &g = sk[8];
-                g.desc.push_back(mm_nn(static_cast<const double *>(A[b]), q.lda, dptr(q.oOm), blk, 1, dptr(q.oY), q.m,
-                                       q.m, blk, q.n, 1.0, 0.0, first ? dptr(q.oXsq) : nullptr,
-                                       first ? dptr(q.oCsq) : nullptr));
-                g.tiles_per.push_back(cdiv(q.m, 64));
+                add_nn(sk, mmd(static_cast<const double *>(A[b]), q.lda, dptr(q.oOm), blk, 1, dptr(q.oY), q.m, q.m, blk,
+                               q.n, 1.0, 0.0, first ? dptr(q.oXsq) : nullptr, first ? dptr(q.oCsq) : nullptr),
+                       mixed ? 4 : 8);
                 if (!first) {
                     // two classical Gram-Schmidt passes: H = Q^T Y, Y -= Q H
                     for (int pass = 0; pass < 2; ++pass) {
-                        MMGroup &gt = (pass ? tn2 : tn1)[8];
-                        gt.desc.push_back(mm_nn(dptr(q.oQ), q.m, dptr(q.oY), q.m, 0, dptr(q.oH), q.cap, q.m, blk, q.ell,
-                                                1.0, 0.0, nullptr, nullptr));
-                        gt.tiles_per.push_back(1);
-                        MMGroup &gn = (pass ? nn2 : nn1)[8];
-                        gn.desc.push_back(mm_nn(dptr(q.oQ), q.m, dptr(q.oH), q.cap, 0, dptr(q.oY), q.m, q.m, blk, q.ell,
-                                                -1.0, 1.0, nullptr, pass ? dptr(q.oCsq) : nullptr));
-                        gn.tiles_per.push_back(cdiv(q.m, 64));
+                        add_tn(pass ? tn2 : tn1,
+                               mmd(dptr(q.oQ), q.m, dptr(q.oY), q.m, 0, dptr(q.oH), q.cap, q.m, blk, q.ell, 1.0, 0.0,
+                                   nullptr, nullptr));
+                        add_nn(pass ? nn2 : nn1,
+                               mmd(dptr(q.oQ), q.m, dptr(q.oH), q.cap, 0, dptr(q.oY), q.m, q.m, blk, q.ell, -1.0, 1.0,
+                                   nullptr, pass ? dptr(q.oCsq) : nullptr),
+                               8);
                     }
                 }
-                QrDesc qd;
-                qd.A = dptr(q.oY); qd.m = q.m; qd.n = blk; qd.lda = q.m; qd.trans = 0;
-                qd.Q = dptr(q.oQ) + (size_t)q.ell * q.m; qd.ldq = q.m; qd.R = nullptr; qd.ldr = 0;
-                qv.push_back(qd);
+                qv.push_back(qrdesc(dptr(q.oY), q.m, blk, q.m, dptr(q.oQ) + (size_t)q.ell * q.m, q.m, nullptr, 0));
                 hgi[i] = GrowItem{b, blk, first, 0};
                 q.ell += blk;
             }
@@ -618,7 +753,7 @@ extern "C" int batched_rsvd(bsvd_ctx *ctx, int batch, const int *m, const int *n
             c->prof_end(pi, 0.0, 0.0);
             if ((rc = readback(G))) return rc;
             std::vector<int> still;
-            for (int i = 0; i < G; ++i) (rb[i] ? pend_check : still).push_back(grow[i]);
+            for (int i = 0; i < G; ++i) (rbv()[i] ? pend_check : still).push_back(grow[i]);
             grow.swap(still);
         }
         if (!pend_check.empty()) {
@@ -629,10 +764,15 @@ extern "C" int batched_rsvd(bsvd_ctx *ctx, int batch, const int *m, const int *n
             for (int i = 0; i < P; ++i) {
                 const int b = pend_check[i];
                 const Inst &q = I[b];
-                MMGroup &g = bt[nmax_for(q.ell)];
-                g.desc.push_back(mm_nn(static_cast<const double *>(A[b]), q.lda, dptr(q.oQ), q.m, 0, dptr(q.oBt), q.n,
-                                       q.m, q.ell, q.n, 1.0, 0.0, nullptr, dptr(q.oBsq)));
-                g.tiles_per.push_back(cdiv(q.n, 64));
+                // B^T = A^T Q into the sample storage (no longer needed once the basis is checked); a
+                // basis wider than 256 columns takes a second pass for the rest, with its own sums
+                const int w1 = std::min(q.ell, 256);
+                add_tn(bt, mmd(static_cast<const double *>(A[b]), q.lda, dptr(q.oQ), q.m, 0, dptr(q.oY), q.n, q.m, w1,
+                               q.n, 1.0, 0.0, nullptr, dptr(q.oBsq)));
+                if (q.ell > 256)
+                    add_tn(bt, mmd(static_cast<const double *>(A[b]), q.lda, dptr(q.oQ) + (size_t)256 * q.m, q.m, 0,
+                                   dptr(q.oY) + (size_t)256 * q.n, q.n, q.m, q.ell - 256, q.n, 1.0, 0.0, nullptr,
+                                   dptr(q.oBsq2)));
             }
             int *dl;
             int *hl = p.put<int>(P, &dl);
@@ -649,7 +789,7 @@ extern "C" int batched_rsvd(bsvd_ctx *ctx, int batch, const int *m, const int *n
             if ((rc = readback(P))) return rc;
             for (int i = 0; i < P; ++i) {
                 const int b = pend_check[i];
-                if (rb[i] || I[b].ell >= I[b].cap || (flags & BSVD_RSVD_FIXED))
+                if (rbv()[i] || I[b].ell >= I[b].cap || (flags & BSVD_RSVD_FIXED))
                     finished.push_back(b);
                 else
                     grow.push_back(b);
@@ -658,14 +798,25 @@ extern "C" int batched_rsvd(bsvd_ctx *ctx, int batch, const int *m, const int *n
         }
     }
 
-    // ---- phase D: QR(B^T), Jacobi SVD of R_B^T, truncation -----------------------------------
+    // ---- phase D: QR(B^T), SVD of R_B, truncation ---------------------------------------------
     std::sort(finished.begin(), finished.end());
     const int F = (int)finished.size();
     {
+        // wide bases: blocked Gram-Schmidt QR of B^T first (its own rounds)
+        std::vector<PanelJob> wide;
+        for (int b : finished) {
+            const Inst &q = I[b];
+            if (q.ell > PANEL)
+                wide.push_back(PanelJob{b, q.n, q.ell, dptr(q.oY), dptr(q.oQB), dptr(q.oRB), dptr(q.oH), dptr(q.oT),
+                                        dptr(q.oT) + PANEL * PANEL, q.cap, q.cap});
+        }
+        if (!wide.empty() && (rc = panel_qr(wide))) return rc;
+
         Packer p;
         if ((rc = new_packer(p))) return rc;
         std::vector<QrDesc> qv;
         std::map<JKey, std::vector<int>> jb;
+        std::vector<int> blk_pos;  // positions (in `finished`) of the bases wider than one panel
         SvdDesc *dsd;
         SvdDesc *hsd = p.put<SvdDesc>(F, &dsd);
         int *dl;
@@ -674,19 +825,21 @@ extern "C" int batched_rsvd(bsvd_ctx *ctx, int batch, const int *m, const int *n
         for (int i = 0; i < F; ++i) {
             const int b = finished[i];
             const Inst &q = I[b];
-            QrDesc qd;
-            qd.A = dptr(q.oBt); qd.m = q.n; qd.n = q.ell; qd.lda = q.n; qd.trans = 0;
-            qd.Q = dptr(q.oQB); qd.ldq = q.n; qd.R = dptr(q.oRB); qd.ldr = q.cap;
-            qv.push_back(qd);
+            hl[i] = b;
+            SvdDesc &d = hsd[i];
+            std::memset(&d, 0, sizeof d);
+            if (q.ell > PANEL) {
+                blk_pos.push_back(i);
+                continue;
+            }
+            qv.push_back(qrdesc(dptr(q.oY), q.n, q.ell, q.n, dptr(q.oQB), q.n, dptr(q.oRB), q.cap));
             // SVD of R_B^T: rotate the rows of R_B; the kernel sends the normalised columns of the
             // working matrix R_B^T (= U_R) to .V and the accumulated rotations (= V_R) to .U.
-            SvdDesc &d = hsd[i];
             d.A = dptr(q.oRB); d.m = q.ell; d.n = q.ell; d.lda = q.cap; d.trans = 1; d.M = q.ell; d.N = q.ell;
             d.S = dptr(q.oSig); d.U = dptr(q.oVR); d.ldu = q.cap; d.V = dptr(q.oUR); d.ldv = q.cap;
             JKey k;
             if (choose_jacobi(0, q.ell, q.ell, 0, &k)) return c->fail(BSVD_EUNSUP, "internal: no Jacobi kernel");
             jb[k].push_back(i);
-            hl[i] = b;
         }
         // Jacobi lists index the descriptor array (position i), finalize lists index instances
         std::vector<std::pair<JKey, std::pair<const int *, int>>> jl;
@@ -725,10 +878,35 @@ extern "C" int batched_rsvd(bsvd_ctx *ctx, int batch, const int *m, const int *n
             c->prof_end(pi, jbytes[L.first], 0.0);
             if (pi >= 0) jrec.push_back({pi, &jb[L.first]});
         }
+        if (!blk_pos.empty()) {
+            // block Jacobi on the columns of R_B (in the auxiliary workspace): left vectors -> V_R,
+            // right vectors -> U_R; info and sweeps by position
+            const int nb = (int)blk_pos.size();
+            std::vector<int> bm(F, 0), bn(F, 0), blda(F, 1), bldu(F, 1);
+            std::vector<const void *> bA(F, nullptr);
+            std::vector<void *> bS(F, nullptr), bU(F, nullptr), bV(F, nullptr);
+            for (int i : blk_pos) {
+                const Inst &q = I[finished[i]];
+                bm[i] = q.ell;
+                bn[i] = q.ell;
+                blda[i] = q.cap;
+                bldu[i] = q.cap;
+                bA[i] = dptr(q.oRB);
+                bS[i] = dptr(q.oSig);
+                bU[i] = dptr(q.oVR);
+                bV[i] = dptr(q.oUR);
+            }
+            AuxWorkspace aux(c);
+            rc = block_jacobi_run(c, BSVD_F64, BLOCK_W, blk_pos, bm.data(), bn.data(), bA.data(), blda.data(), bS.data(),
+                                  bU.data(), bldu.data(), bV.data(), bldu.data(), 1e-15, 60, djsweeps, djinfo);
+            if (rc) return rc;
+            (void)nb;
+        }
         pi = c->prof_begin(BSVD_STAGE_SMALL, "finalize_kernel");
         e = launch_finalize(dstate, dl, F, rank, err_est, info, djinfo, drankc, samples, c->stream);
         if (e != hipSuccess) return c->hip_fail(e, "finalize launch");
         c->prof_end(pi, 0.0, 0.0);
+        if ((rc = c->ensure_readback(2 * sizeof(int) * (size_t)batch))) return rc;
         e = hipMemcpyAsync(c->rb, drankc, sizeof(int) * (size_t)F, hipMemcpyDeviceToHost, c->stream);
         if (e != hipSuccess) return c->hip_fail(e, "hipMemcpyAsync(rank)");
         if (!jrec.empty()) {
@@ -740,14 +918,14 @@ extern "C" int batched_rsvd(bsvd_ctx *ctx, int batch, const int *m, const int *n
         if (e != hipSuccess) return c->hip_fail(e, "hipStreamSynchronize");
         for (auto &jr : jrec) {
             double fl = 0.0;
-            for (int i : *jr.second) fl += jacobi_flops(I[finished[i]].ell, I[finished[i]].ell, rb[F + i]);
+            for (int i : *jr.second) fl += jacobi_flops(I[finished[i]].ell, I[finished[i]].ell, rbv()[F + i]);
             c->recs[jr.first].flops = fl;
         }
     }
     // ---- back-transform U = Q U_R[:, :k], V = Q_B V_R[:, :k] ---------------------------------
     {
         std::vector<int> kk(F);
-        for (int i = 0; i < F; ++i) kk[i] = rb[i];
+        for (int i = 0; i < F; ++i) kk[i] = rbv()[i];
         Packer p;
         if ((rc = new_packer(p))) return rc;
         std::map<int, MMGroup> out;
@@ -756,22 +934,88 @@ extern "C" int batched_rsvd(bsvd_ctx *ctx, int batch, const int *m, const int *n
             const Inst &q = I[b];
             const int k = kk[i];
             if (k <= 0) continue;
-            MMGroup &g = out[nmax_for(k)];
-            if (U && U[b]) {
-                g.desc.push_back(mm_nn(dptr(q.oQ), q.m, dptr(q.oUR), q.cap, 0, static_cast<double *>(U[b]), ldu[b], q.m,
-                                       k, q.ell, 1.0, 0.0, nullptr, nullptr));
-                g.tiles_per.push_back(cdiv(q.m, 64));
-            }
-            if (V && V[b]) {
-                g.desc.push_back(mm_nn(dptr(q.oQB), q.n, dptr(q.oVR), q.cap, 0, static_cast<double *>(V[b]), ldv[b], q.n,
-                                       k, q.ell, 1.0, 0.0, nullptr, nullptr));
-                g.tiles_per.push_back(cdiv(q.n, 64));
-            }
+            if (U && U[b])
+                add_nn(out, mmd(dptr(q.oQ), q.m, dptr(q.oUR), q.cap, 0, static_cast<double *>(U[b]), ldu[b], q.m, k, q.ell,
+                                1.0, 0.0, nullptr, nullptr),
+                       8);
+            if (V && V[b])
+                add_nn(out, mmd(dptr(q.oQB), q.n, dptr(q.oVR), q.cap, 0, static_cast<double *>(V[b]), ldv[b], q.n, k,
+                                q.ell, 1.0, 0.0, nullptr, nullptr),
+                       8);
         }
         std::vector<Pending> mo;
         pack_mm(p, out, 0, mo);
         if ((rc = commit(p))) return rc;
         if ((rc = launch_mm(mo, BSVD_STAGE_OUTPUT))) return rc;
+    }
+    return BSVD_OK;
+}
+
+extern "C" int batched_rsvd(bsvd_ctx *ctx, int batch, const int *m, const int *n, const void *const *A,
+                            const int *lda, const double *eps, const int *max_rank, void *const *S, void *const *U,
+                            const int *ldu, void *const *V, const int *ldv, int *rank, double *err_est, int *info,
+                            unsigned long long seed, unsigned flags, const int *ell0, int *samples) {
+    if (!ctx) return BSVD_EARG;
+    Ctx *c = reinterpret_cast<Ctx *>(ctx);
+    c->err.clear();
+    if (batch < 0) return c->fail(BSVD_EARG, "batch = %d < 0", batch);
+    if (batch == 0) return BSVD_OK;
+    if (!m || !n || !A || !lda || !max_rank || !S) return c->fail(BSVD_EARG, "m, n, A, lda, max_rank and S must be non-NULL");
+    if (U && !ldu) return c->fail(BSVD_EARG, "U given without ldu");
+    if (V && !ldv) return c->fail(BSVD_EARG, "V given without ldv");
+    if ((flags & BSVD_RSVD_FIXED) && !ell0) return c->fail(BSVD_EARG, "BSVD_RSVD_FIXED needs ell0");
+    if ((flags & BSVD_RSVD_LEARNED) && (ell0 || (flags & BSVD_RSVD_FIXED)))
+        return c->fail(BSVD_EARG, "BSVD_RSVD_LEARNED chooses ell0 itself (pass ell0 = NULL, no FIXED)");
+    if ((flags & BSVD_RSVD_LEARNED) && !c->model) return c->fail(BSVD_EARG, "BSVD_RSVD_LEARNED needs a rank model");
+    if (flags & ~(unsigned)(BSVD_RSVD_FIXED | BSVD_RSVD_LEARNED | BSVD_RSVD_MIXED))
+        return c->fail(BSVD_EUNSUP, "flags 0x%x not supported", flags);
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return c->hip_fail(e, "hipSetDevice");
+    for (int b = 0; b < batch; ++b) {
+        if (m[b] < 1) return c->fail(BSVD_EARG, "instance %d: m = %d < 1", b, m[b]);
+        if (n[b] < 1) return c->fail(BSVD_EARG, "instance %d: n = %d < 1", b, n[b]);
+        if (m[b] > 512 || n[b] > 512)
+            return c->fail(BSVD_EUNSUP, "instance %d: %d x %d exceeds the 512 x 512 limit", b, m[b], n[b]);
+        if (lda[b] < m[b]) return c->fail(BSVD_EARG, "instance %d: lda = %d < m = %d", b, lda[b], m[b]);
+        if (!A[b]) return c->fail(BSVD_EARG, "instance %d: A is NULL", b);
+        if (!S[b]) return c->fail(BSVD_EARG, "instance %d: S is NULL", b);
+        if (max_rank[b] < 1) return c->fail(BSVD_EARG, "instance %d: max_rank = %d < 1", b, max_rank[b]);
+        if (U && U[b] && ldu[b] < m[b]) return c->fail(BSVD_EARG, "instance %d: ldu = %d < m = %d", b, ldu[b], m[b]);
+        if (V && V[b] && ldv[b] < n[b]) return c->fail(BSVD_EARG, "instance %d: ldv = %d < n = %d", b, ldv[b], n[b]);
+        if (eps && !(eps[b] > 0.0 && eps[b] < 1.0))
+            return c->fail(BSVD_EARG, "instance %d: eps = %g not in (0, 1)", b, eps[b]);
+        if ((flags & BSVD_RSVD_FIXED) && ell0[b] < 1) return c->fail(BSVD_EARG, "instance %d: ell0 < 1 with FIXED", b);
+    }
+    // sub-batches of consecutive instances whose workspace stays within the budget
+    // (BSVD_RSVD_BUDGET_MB in the environment lowers the bound, e.g. to exercise the split)
+    size_t budget = WS_BUDGET;
+    {
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) == hipSuccess && fr > 0) budget = std::min(budget, (fr + c->dws_size) / 2);
+        const char *env = std::getenv("BSVD_RSVD_BUDGET_MB");
+        if (env && std::atol(env) > 0) budget = std::min(budget, (size_t)std::atol(env) << 20);
+    }
+    const bool learned = (flags & BSVD_RSVD_LEARNED) != 0;
+    int b0 = 0;
+    while (b0 < batch) {
+        size_t acc = 0;
+        int b1 = b0;
+        while (b1 < batch) {
+            const int cap = std::min(std::min(std::min(m[b1], n[b1]), CAPMAX), max_rank[b1] + CAP_OVER);
+            const int e0 = learned ? cap : (ell0 ? std::min(std::max(ell0[b1], 0), cap) : 0);
+            const size_t need = inst_bytes(m[b1], n[b1], cap, std::max(std::max(GROW_BLK, e0), PROBE_COLS)) + 1024;
+            if (b1 > b0 && acc + need > budget) break;
+            acc += need;
+            ++b1;
+        }
+        const int cnt = b1 - b0;
+        int rc = rsvd_range(c, b0, cnt, m + b0, n + b0, A + b0, lda + b0, eps ? eps + b0 : nullptr, max_rank + b0,
+                            S + b0, U ? U + b0 : nullptr, U ? ldu + b0 : nullptr, V ? V + b0 : nullptr,
+                            V ? ldv + b0 : nullptr, rank ? rank + b0 : nullptr, err_est ? err_est + b0 : nullptr,
+                            info ? info + b0 : nullptr, seed, flags, ell0 ? ell0 + b0 : nullptr,
+                            samples ? samples + b0 : nullptr);
+        if (rc) return rc;
+        b0 = b1;
     }
     return BSVD_OK;
 }

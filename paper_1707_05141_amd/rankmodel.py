@@ -25,8 +25,8 @@ def labels_and_features(buf, offs, m, n, eps=1e-6, seed=0, max_rank=64):
 
 
 def train_packed(buf, offs, m, n, *, eps=1e-6, seed=0, epochs=150, batch=256, lr=2e-3, oversample=6.0,
-                 coverage=0.98, device=None):
-    feats, ranks, ok = labels_and_features(buf, offs, m, n, eps=eps, seed=seed)
+                 coverage=0.98, device=None, max_rank=64):
+    feats, ranks, ok = labels_and_features(buf, offs, m, n, eps=eps, seed=seed, max_rank=max_rank)
     idx = np.nonzero(ok)[0]
     X = feats[torch.from_numpy(idx).to(feats.device)]
     T = torch.from_numpy((ranks[idx] / 16.0).astype(np.float32))

@@ -169,31 +169,43 @@ def c5_mixture(count, seed, sizes=SIZES_UNEVEN):
     return m, n, kinds, w
 
 
+def _householder_haar(G):
+    import torch
+    Qh, Rh = torch.linalg.qr(G)
+    d = torch.sign(torch.diagonal(Rh, dim1=-2, dim2=-1))
+    d[d == 0] = 1.0
+    return Qh * d[:, None, :]
+
+
 def _orth_haar(G):
     """Q with positive diag(R) of each matrix of the stack G (B x rows x k, rows >= k, FP64): the Q
     factor of a Gaussian matrix normalised this way is Haar distributed. Computed as Cholesky QR
-    applied twice (Q = G R^-1 with R^T R = G^T G; the second pass restores orthogonality to rounding
+    applied twice (Q = G L^-T with L L^T = G^T G; the second pass restores orthogonality to rounding
     level); any matrix whose Cholesky factorisation fails or whose result is not orthonormal to 1e-13
-    is redone by Householder QR with the signs of diag(R) folded into Q."""
+    is redone by Householder QR with the signs of diag(R) folded into Q (so is the whole stack if a
+    library call of the fast path fails)."""
     import torch
     B, _, k = G.shape
-    Q = G
-    bad = torch.zeros(B, dtype=torch.bool, device=G.device)
-    for _ in range(2):
-        C = torch.bmm(Q.transpose(1, 2).contiguous(), Q)
-        L, info = torch.linalg.cholesky_ex(C)
-        bad |= info != 0
-        L[bad] = torch.eye(k, dtype=G.dtype, device=G.device)
-        Q = torch.linalg.solve_triangular(L, Q.transpose(1, 2).contiguous(), upper=False).transpose(1, 2).contiguous()
-    E = torch.bmm(Q.transpose(1, 2).contiguous(), Q) - torch.eye(k, dtype=G.dtype, device=G.device)
-    bad |= ~torch.isfinite(E).all(dim=(1, 2))
-    bad |= E.abs().amax(dim=(1, 2)) > 1e-13
+    eye = torch.eye(k, dtype=G.dtype, device=G.device)
+    try:
+        Q = G
+        bad = torch.zeros(B, dtype=torch.bool, device=G.device)
+        for _ in range(2):
+            C = torch.bmm(Q.transpose(1, 2).contiguous(), Q)
+            L, info = torch.linalg.cholesky_ex(C)
+            bad |= info != 0
+            L[bad] = eye
+            Linv, info2 = torch.linalg.inv_ex(L)
+            bad |= info2 != 0
+            Q = torch.bmm(Q, Linv.transpose(1, 2).contiguous())
+        E = torch.bmm(Q.transpose(1, 2).contiguous(), Q) - eye
+        bad |= ~torch.isfinite(E).all(dim=(1, 2))
+        bad |= E.abs().amax(dim=(1, 2)) > 1e-13
+    except RuntimeError:
+        return _householder_haar(G)
     if bad.any():
         idx = torch.nonzero(bad).flatten()
-        Qh, Rh = torch.linalg.qr(G[idx])
-        d = torch.sign(torch.diagonal(Rh, dim1=-2, dim2=-1))
-        d[d == 0] = 1.0
-        Q[idx] = Qh * d[:, None, :]
+        Q[idx] = _householder_haar(G[idx])
     return Q
 
 
