@@ -501,7 +501,9 @@ def run_c5(args, torch, P, synth):
                                blocks_compared=int(both.sum()),
                                histogram={str(int(v)): int(c) for v, c in zip(*np.unique(diff[both], return_counts=True))}),
                            sampled_oracle_rank_mismatch_plain=nbad, max_err_est=float(learned["err"][ok].max()),
-                           model=model.stats, train_s=train_s, generation_s=gen_s, kernels=table),
+                           model=model.stats, train_s=train_s, generation_s=gen_s, kernels=table,
+                           tuned_block_width={str(k): P.tune_get(1, 0, k, k) for k in range(96, 513, 32)
+                                              if P.tune_get(1, 0, k, k) is not None}),
                roofline=roof)
     if args.cpu_baseline:
         res["cpu_baseline"] = cpu_baseline_c5(buf, offs, m, n, kinds_a, oseed, eps, max_rank, oracle)

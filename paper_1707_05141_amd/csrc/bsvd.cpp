@@ -131,8 +131,8 @@ void Ctx::prof_end(int idx, double bytes, double flops) {
 // throughput regime of a large batch rather than the latency of a few matrices.
 int tune_block_width(Ctx *c, int dtype, int M, int N, const std::vector<int> &cls, const int *m, const int *n,
                      const void *const *A, const int *lda, void *const *S, void *const *U, const int *ldu,
-                     void *const *V, const int *ldv, double tol, int max_sweeps, int *bw) {
-    const auto key = std::make_tuple(0, dtype, M, N);
+                     void *const *V, const int *ldv, double tol, int max_sweeps, int *bw, int kind) {
+    const auto key = std::make_tuple(kind, dtype, M, N);
     auto it = c->tune.find(key);
     if (it != c->tune.end()) {
         *bw = it->second;

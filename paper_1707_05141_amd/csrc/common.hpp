@@ -57,7 +57,7 @@ hipError_t launch_gemm_small(int dtype, const GemmDesc *d, const int *list, int 
 struct Ctx;
 int tune_block_width(Ctx *c, int dtype, int M, int N, const std::vector<int> &cls, const int *m, const int *n,
                      const void *const *A, const int *lda, void *const *S, void *const *U, const int *ldu,
-                     void *const *V, const int *ldv, double tol, int max_sweeps, int *bw);
+                     void *const *V, const int *ldv, double tol, int max_sweeps, int *bw, int kind = 0);
 int block_jacobi_run(Ctx *c, int dtype, int w, const std::vector<int> &insts, const int *m, const int *n,
                      const void *const *A, const int *lda, void *const *S, void *const *U, const int *ldu,
                      void *const *V, const int *ldv, double tol, int max_sweeps, int *sweeps, int *info);

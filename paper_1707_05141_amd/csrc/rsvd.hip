@@ -307,6 +307,14 @@ __global__ void grow_decide_kernel(RsvdState *__restrict__ st, const GrowItem *_
     const double thr = (S.eps / S.safety) * (S.eps / S.safety) * S.normA2;
     S.ell += it.b;
     S.flag = (S.nonfinite || est2 <= thr || S.ell >= S.cap) ? 1 : 0;
+    // An FP32 sample column carries rounding noise of about n u32^2 ||A||_F^2 in squared norm
+    // (u32 = 2^-24). Once the estimate is within 256x of that floor (16x in norm), the directions
+    // still to be found would come out of FP32 samples with more than ~6% noise in them, wasting
+    // basis columns: the growth goes on in FP64 (flag 2).
+    if (!S.flag && it.f32) {
+        const double u32 = 5.9604644775390625e-08;
+        if (est2 <= 256.0 * (double)S.n * u32 * u32 * S.normA2) S.flag = 2;
+    }
     flags[t] = S.flag;
 }
 
@@ -332,7 +340,7 @@ __global__ void check_kernel(RsvdState *__restrict__ st, const int *__restrict__
     if (S.ell > 256) b2 += dd_sum_pairs(S.bsq2, S.ntile_n);
     S.normB2 = b2;
     S.check_ok = (S.normA2 - b2) <= S.eps * S.eps * S.normA2 ? 1 : 0;
-    S.flag = S.check_ok | S.nonfinite;
+    S.flag = ((S.normA2 - b2) <= S.accept * S.eps * S.eps * S.normA2 ? 1 : 0) | S.nonfinite;
     flags[t] = S.flag;
 }
 

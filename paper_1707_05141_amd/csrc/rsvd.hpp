@@ -32,14 +32,15 @@ struct RsvdState {
     double *sig;              // singular values of R_B^T (capacity cap)
     double *Sout;             // caller's S
     double normA2, normB2, eps, safety;
+    double accept;  // a checked basis is final when ||A||^2 - ||B||^2 <= accept eps^2 ||A||^2
     int m, n, lda, cap, ell, max_rank;
     int ntile_m, ntile_n;
     int flag, check_ok, nonfinite, rank;
 };
 
-// One entry of a growth round: instance, block size, first block flag.
+// One entry of a growth round: instance, block size, first block flag, FP32 sample block flag.
 struct GrowItem {
-    int inst, b, first, pad;
+    int inst, b, first, f32;
 };
 
 // Block operation on dst (rows x cols, ld ldd): mode 0 dst += src, 1 dst = 0, 2 dst = src

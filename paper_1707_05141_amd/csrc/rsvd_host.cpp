@@ -51,9 +51,9 @@ constexpr int CAPMAX = 512;
 constexpr int CAP_OVER = 32;  // basis columns allowed beyond max_rank
 constexpr int PANEL = 64;     // widest matrix of the one-kernel QR / small Jacobi paths
 constexpr int GROW_BLK = 8;
-constexpr int BLOCK_W = 16;   // block width of the block Jacobi on R_B for ell > PANEL
+constexpr int BLOCK_W = 16;   // block width of the block Jacobi on R_B if the tuner finds none
 constexpr double SAFETY = 2.0;
-constexpr size_t WS_BUDGET = (size_t)24 << 30;  // workspace bound of one sub-batch
+constexpr size_t WS_BUDGET = (size_t)96 << 30;  // workspace bound of one sub-batch
 
 // NMAX class of the lane-per-row GEMM (N <= 64) and of the X^T Y GEMM (N <= 256)
 inline int nmax_for(int x) { return x <= 8 ? 8 : (x <= 16 ? 16 : (x <= 32 ? 32 : 64)); }
@@ -62,6 +62,7 @@ inline int cdiv(int a, int b) { return (a + b - 1) / b; }
 
 struct Inst {
     int m, n, lda, cap, ell, ell0, maxr;
+    bool f32;  // next sample block in FP32 (mixed mode until the instance fails an exact check)
     size_t oQ, oY, oOm, oH, oT, oQB, oRB, oUR, oVR, oSig, oXsq, oCsq, oBsq, oBsq2;
 };
 
@@ -278,6 +279,7 @@ static int rsvd_range(Ctx *c, int inst_base, int batch, const int *m, const int 
         q.ell = 0;
         q.ell0 = ell0 ? std::min(std::max(ell0[b], 0), q.cap) : 0;
         q.maxr = max_rank[b];
+        q.f32 = mixed;
         if (learned) q.ell0 = q.cap;  // the learned count is at most cap: size buffers for it
         const int bmax = std::max(std::max(GROW_BLK, q.ell0), PROBE_COLS);
         const int pan = cdiv(q.cap, PANEL);
@@ -343,6 +345,10 @@ static int rsvd_range(Ctx *c, int inst_base, int batch, const int *m, const int 
             s.Sout = static_cast<double *>(S[b]);
             s.eps = eps ? eps[b] : 1e-6;
             s.safety = SAFETY;
+            // plain: final once the check meets eps (the estimator has already asked for eps / 2);
+            // with a learned or FP32 first block the check itself asks for eps / 2, so that the
+            // truncation keeps most of the budget (the rank stays that of the plain method)
+            s.accept = (learned || mixed) ? 1.0 / (SAFETY * SAFETY) : 1.0;
             s.m = q.m;
             s.n = q.n;
             s.lda = q.lda;
@@ -621,7 +627,12 @@ static int rsvd_range(Ctx *c, int inst_base, int batch, const int *m, const int 
         if (e != hipSuccess) return c->hip_fail(e, "ell0 launch");
         c->prof_end(pi, 0.0, 0.0);
         if ((rc = readback(batch))) return rc;
-        for (int b = 0; b < batch; ++b) I[b].ell0 = rbv()[b];
+        for (int b = 0; b < batch; ++b) {
+            I[b].ell0 = rbv()[b];
+            // a wide predicted basis means a slowly decaying spectrum, whose directions near the
+            // truncation sit at the FP32 noise level (about sqrt(n) u32 of ||A||_F): sample in FP64
+            if (I[b].ell0 > PANEL) I[b].f32 = false;
+        }
     }
 
     // ---- phase A: initial block of ell0 samples (Algorithm 4 as printed) -------------------
@@ -635,7 +646,7 @@ static int rsvd_range(Ctx *c, int inst_base, int batch, const int *m, const int 
             RngDesc *drd;
             RngDesc *hrd = p.put<RngDesc>(init.size(), &drd);
             std::vector<int2> rt;
-            std::map<int, MMGroup> sk;
+            std::map<int, MMGroup> sk, sk32;
             std::vector<QrDesc> qv;
             GrowItem *dgi;
             GrowItem *hgi = p.put<GrowItem>(init.size(), &dgi);
@@ -645,12 +656,13 @@ static int rsvd_range(Ctx *c, int inst_base, int batch, const int *m, const int 
             for (size_t i = 0; i < init.size(); ++i) {
                 const int b = init[i];
                 Inst &q = I[b];
-                hrd[i] = RngDesc{dptr(q.oOm), q.n, q.ell0, 0, q.ell0, inst_base + b, mixed ? 1 : 0};
-                rgb += (mixed ? 4.0 : 8.0) * q.n * (double)q.ell0;
+                hrd[i] = RngDesc{dptr(q.oOm), q.n, q.ell0, 0, q.ell0, inst_base + b, q.f32 ? 1 : 0};
+                rgb += (q.f32 ? 4.0 : 8.0) * q.n * (double)q.ell0;
                 for (int t = 0; t < cdiv(q.n * q.ell0, 256); ++t) rt.push_back(make_int2((int)i, t));
-                add_nn(sk, mmd(static_cast<const double *>(A[b]), q.lda, dptr(q.oOm), q.ell0, 1, dptr(q.oY), q.m, q.m,
-                               q.ell0, q.n, 1.0, 0.0, dptr(q.oXsq), nullptr),
-                       mixed ? 4 : 8);
+                add_nn(q.f32 ? sk32 : sk,
+                       mmd(static_cast<const double *>(A[b]), q.lda, dptr(q.oOm), q.ell0, 1, dptr(q.oY), q.m, q.m, q.ell0,
+                           q.n, 1.0, 0.0, dptr(q.oXsq), nullptr),
+                       q.f32 ? 4 : 8);
                 if (q.ell0 <= PANEL)
                     qv.push_back(qrdesc(dptr(q.oY), q.m, q.ell0, q.m, dptr(q.oQ), q.m, nullptr, 0));
                 else
@@ -663,7 +675,8 @@ static int rsvd_range(Ctx *c, int inst_base, int batch, const int *m, const int 
             int2 *hrt = p.put<int2>(rt.size(), &drt);
             if (hrt) std::copy(rt.begin(), rt.end(), hrt);
             std::vector<Pending> mm;
-            pack_mm(p, sk, mixed ? 2 : 0, mm);
+            pack_mm(p, sk, 0, mm);
+            pack_mm(p, sk32, 2, mm);
             QrDesc *dq;
             std::vector<QLaunch> ql;
             if ((rc = pack_qr(p, qv, ql, &dq))) return c->fail(rc, "internal: no QR kernel for the initial block");
@@ -695,7 +708,7 @@ static int rsvd_range(Ctx *c, int inst_base, int batch, const int *m, const int 
             GrowItem *hgi = p.put<GrowItem>(G, &dgi);
             if (!hrd || !hgi) return commit(p);
             std::vector<int2> rt;
-            std::map<int, MMGroup> sk, tn1, nn1, tn2, nn2;
+            std::map<int, MMGroup> sk, sk32, tn1, nn1, tn2, nn2;
             std::vector<QrDesc> qv;
             double rgb = 0;
             for (int i = 0; i < G; ++i) {
@@ -703,12 +716,13 @@ static int rsvd_range(Ctx *c, int inst_base, int batch, const int *m, const int 
                 Inst &q = I[b];
                 const int blk = std::min(GROW_BLK, q.cap - q.ell);
                 const int first = q.ell == 0;
-                rgb += (mixed ? 4.0 : 8.0) * q.n * (double)blk;
-                hrd[i] = RngDesc{dptr(q.oOm), q.n, blk, q.ell, blk, inst_base + b, mixed ? 1 : 0};
+                rgb += (q.f32 ? 4.0 : 8.0) * q.n * (double)blk;
+                hrd[i] = RngDesc{dptr(q.oOm), q.n, blk, q.ell, blk, inst_base + b, q.f32 ? 1 : 0};
                 for (int t = 0; t < cdiv(q.n * blk, 256); ++t) rt.push_back(make_int2(i, t));
-                add_nn(sk, mmd(static_cast<const double *>(A[b]), q.lda, dptr(q.oOm), blk, 1, dptr(q.oY), q.m, q.m, blk,
-                               q.n, 1.0, 0.0, first ? dptr(q.oXsq) : nullptr, first ? dptr(q.oCsq) : nullptr),
-                       mixed ? 4 : 8);
+                add_nn(q.f32 ? sk32 : sk,
+                       mmd(static_cast<const double *>(A[b]), q.lda, dptr(q.oOm), blk, 1, dptr(q.oY), q.m, q.m, blk, q.n,
+                           1.0, 0.0, first ? dptr(q.oXsq) : nullptr, first ? dptr(q.oCsq) : nullptr),
+                       q.f32 ? 4 : 8);
                 if (!first) {
                     // two classical Gram-Schmidt passes: H = Q^T Y, Y -= Q H
                     for (int pass = 0; pass < 2; ++pass) {
@@ -722,14 +736,15 @@ static int rsvd_range(Ctx *c, int inst_base, int batch, const int *m, const int 
                     }
                 }
                 qv.push_back(qrdesc(dptr(q.oY), q.m, blk, q.m, dptr(q.oQ) + (size_t)q.ell * q.m, q.m, nullptr, 0));
-                hgi[i] = GrowItem{b, blk, first, 0};
+                hgi[i] = GrowItem{b, blk, first, q.f32 ? 1 : 0};
                 q.ell += blk;
             }
             int2 *drt;
             int2 *hrt = p.put<int2>(rt.size(), &drt);
             if (hrt) std::copy(rt.begin(), rt.end(), hrt);
             std::vector<Pending> msk, mt1, mn1, mt2, mn2;
-            pack_mm(p, sk, mixed ? 2 : 0, msk);
+            pack_mm(p, sk, 0, msk);
+            pack_mm(p, sk32, 2, msk);
             pack_mm(p, tn1, 1, mt1);
             pack_mm(p, nn1, 0, mn1);
             pack_mm(p, tn2, 1, mt2);
@@ -753,7 +768,11 @@ static int rsvd_range(Ctx *c, int inst_base, int batch, const int *m, const int 
             c->prof_end(pi, 0.0, 0.0);
             if ((rc = readback(G))) return rc;
             std::vector<int> still;
-            for (int i = 0; i < G; ++i) (rbv()[i] ? pend_check : still).push_back(grow[i]);
+            for (int i = 0; i < G; ++i) {
+                const int fl = rbv()[i];
+                (fl == 1 ? pend_check : still).push_back(grow[i]);
+                if (fl == 2) I[grow[i]].f32 = false;
+            }
             grow.swap(still);
         }
         if (!pend_check.empty()) {
@@ -789,10 +808,12 @@ static int rsvd_range(Ctx *c, int inst_base, int batch, const int *m, const int 
             if ((rc = readback(P))) return rc;
             for (int i = 0; i < P; ++i) {
                 const int b = pend_check[i];
-                if (rbv()[i] || I[b].ell >= I[b].cap || (flags & BSVD_RSVD_FIXED))
+                if (rbv()[i] || I[b].ell >= I[b].cap || (flags & BSVD_RSVD_FIXED)) {
                     finished.push_back(b);
-                else
+                } else {
                     grow.push_back(b);
+                    I[b].f32 = false;  // the FP32 samples did not reach the tolerance: go on in FP64
+                }
             }
             pend_check.clear();
         }
@@ -897,9 +918,26 @@ static int rsvd_range(Ctx *c, int inst_base, int batch, const int *m, const int 
                 bV[i] = dptr(q.oUR);
             }
             AuxWorkspace aux(c);
-            rc = block_jacobi_run(c, BSVD_F64, BLOCK_W, blk_pos, bm.data(), bn.data(), bA.data(), blda.data(), bS.data(),
-                                  bU.data(), bldu.data(), bV.data(), bldu.data(), 1e-15, 60, djsweeps, djinfo);
-            if (rc) return rc;
+            // block width per class of padded size (multiples of 32), chosen by the autotuner on the
+            // first call that meets the class (kind 1 of the tuning cache) and reused afterwards
+            std::map<int, std::vector<int>> cls;
+            for (int i : blk_pos) cls[cdiv(bm[i], 32) * 32].push_back(i);
+            std::map<int, std::vector<int>> byw;
+            for (auto &kv : cls) {
+                int w = BLOCK_W;
+                rc = tune_block_width(c, BSVD_F64, kv.first, kv.first, kv.second, bm.data(), bn.data(), bA.data(),
+                                      blda.data(), bS.data(), bU.data(), bldu.data(), bV.data(), bldu.data(), 1e-15, 60,
+                                      &w, 1);
+                if (rc) return rc;
+                auto &v = byw[w];
+                v.insert(v.end(), kv.second.begin(), kv.second.end());
+            }
+            for (auto &kv : byw) {
+                rc = block_jacobi_run(c, BSVD_F64, kv.first, kv.second, bm.data(), bn.data(), bA.data(), blda.data(),
+                                      bS.data(), bU.data(), bldu.data(), bV.data(), bldu.data(), 1e-15, 60, djsweeps,
+                                      djinfo);
+                if (rc) return rc;
+            }
             (void)nb;
         }
         pi = c->prof_begin(BSVD_STAGE_SMALL, "finalize_kernel");

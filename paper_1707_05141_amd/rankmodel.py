@@ -5,7 +5,9 @@ Labels are the ranks that the plain FP64 randomized SVD of this library computes
 the library's probe features. Training runs on the GPU through the library's own forward, backward
 and Adam kernels (``RankModel.train``). The margin added to the prediction is calibrated on the
 training blocks so that the first sample block covers the rank plus an oversampling of ``oversample``
-for the ``coverage`` quantile of the blocks; the rest fall back to adaptive growth.
+for the ``coverage`` quantile of the blocks; the rest fall back to adaptive growth. The quantile is
+moderate (0.8): for high-rank blocks an overshoot costs more (the small SVD grows with the cube of
+the sample count) than the few growth rounds an undershoot adds.
 """
 from __future__ import annotations
 
@@ -25,7 +27,7 @@ def labels_and_features(buf, offs, m, n, eps=1e-6, seed=0, max_rank=64):
 
 
 def train_packed(buf, offs, m, n, *, eps=1e-6, seed=0, epochs=150, batch=256, lr=2e-3, oversample=6.0,
-                 coverage=0.98, device=None, max_rank=64):
+                 coverage=0.8, device=None, max_rank=64):
     feats, ranks, ok = labels_and_features(buf, offs, m, n, eps=eps, seed=seed, max_rank=max_rank)
     idx = np.nonzero(ok)[0]
     X = feats[torch.from_numpy(idx).to(feats.device)]
