@@ -60,9 +60,13 @@ enum {
     BSVD_RSVD_FIXED = 1u << 0,  /* exactly ell0[b] samples, no adaptive growth (Algorithm 4 as printed) */
     BSVD_RSVD_LEARNED = 1u << 1, /* initial sample count from the context's rank model */
     BSVD_RSVD_MIXED = 1u << 2    /* sketch products Y = A Omega in FP32 (Omega drawn in FP32, A rounded
-                                    to FP32 on load, FP32 accumulation); the basis QR, the projection
-                                    B = Q^T A, the exact check, the rank rule and the small SVD stay
-                                    in FP64, so the FP64 check still guarantees the tolerance */
+                                    to FP32 on load, FP32 accumulation) while the samples are well above
+                                    FP32 rounding: an instance goes on in FP64 once the growth estimate
+                                    is within 16 sqrt(n) u32 ||A||_F of the FP32 noise floor, after a
+                                    failed exact check, and (with LEARNED) when the predicted basis is
+                                    wider than 64 columns. The basis QR, the projection B = Q^T A, the
+                                    exact check, the rank rule and the small SVD stay in FP64, so the
+                                    FP64 check still guarantees the tolerance */
 };
 
 /* Create a context bound to `device` (HIP ordinal) and `stream` (a hipStream_t; NULL = the null
@@ -111,7 +115,9 @@ int bsvd_profile_kernels(bsvd_ctx *ctx, char *buf, int cap);
 
 /* Autotuner cache. Without a BSVD_SVD_BLOCK_W* flag, the first batched_svd call that sends a
  * (dtype, M, N) class (M = max(m, n), N = min(m, n)) to the block path times widths 8, 16 and 32 on up
- * to 128 of its instances and keeps the fastest in the context (kind 0).
+ * to 512 of its instances and keeps the fastest in the context (kind 0). batched_rsvd does the same
+ * for the block Jacobi SVD of its R_B factors wider than 64 columns, per class of sizes padded to a
+ * multiple of 32 (kind 1, M = N = the padded size).
  *   bsvd_tune_get   value chosen for (kind, dtype, M, N) and up to max_cand (candidate, ms) pairs
  *                   (host arrays, nullable); BSVD_EARG if the class was never tuned
  *   bsvd_tune_save  write the cache as text lines "kind dtype M N value"
@@ -192,8 +198,14 @@ int batched_qr(bsvd_ctx *ctx, int dtype, int batch, const int *m, const int *n, 
  * drawn, projected against the current basis twice (classical Gram-Schmidt), and the mean squared
  * norm of the projected samples -- an unbiased estimate of ||(I - Q Q^T) A||_F^2 -- stops the
  * growth once it is <= (eps / 2)^2 ||A||_F^2; the orthonormalised block is always appended. The exact
- * test ||A||_F^2 - ||Q^T A||_F^2 <= eps^2 ||A||_F^2 then accepts the basis or resumes growth. The
- * basis is capped at min(m, n, 64) columns.
+ * test ||A||_F^2 - ||Q^T A||_F^2 <= eps^2 ||A||_F^2 (eps^2 / 4 with LEARNED or MIXED, whose first
+ * samples did not come from the estimator) then accepts the basis or resumes growth. The basis is
+ * capped at min(m, n, max_rank + 32) columns. Bases wider than 64 columns are orthonormalised panel
+ * by panel (blocked Gram-Schmidt with reorthogonalisation) and R_B is diagonalised by the block
+ * Jacobi method (Section 6.1). ||A||_F^2 and ||B||_F^2 are summed in double-double arithmetic, and
+ * the truncation residual is ||A||_F^2 - ||B||_F^2 (not ||A||_F^2 - sum sigma^2). A batch whose
+ * workspace would exceed 96 GiB (or half the free device memory) runs in consecutive sub-batches
+ * with identical results.
  *
  * Omega's entry (row r, column j) of instance b is N(0,1) from Philox4x32-10 with counter
  * (r, j, b, 0) and key (seed low, seed high), mapped by Box-Muller; column indices continue across
@@ -204,8 +216,8 @@ int batched_qr(bsvd_ctx *ctx, int dtype, int batch, const int *m, const int *n, 
  *   A, lda       host array of device pointers to FP64 inputs, lda >= m. Not modified.
  *   eps          nullable host double[batch], 0 < eps < 1 (NULL: 1e-6). eps^2 must be well above
  *                the FP64 rounding of ||A||_F^2 (eps >~ 1e-7).
- *   max_rank     host int[batch] >= 1: capacity of S, U, V; a larger exact rank is truncated to it
- *                and sets info = 2
+ *   max_rank     host int[batch] >= 1: capacity of S, U, V (at most min(m, n) columns are ever
+ *                written); a larger exact rank is truncated to it and sets info = 2
  *   S            host array of device pointers: the first rank[b] entries receive sigma, descending
  *   U, ldu       nullable; U[b] (nullable entry) receives m x rank[b] left vectors, ldu >= m
  *   V, ldv       nullable; V[b] (nullable entry) receives n x rank[b] right vectors, ldv >= n

@@ -125,7 +125,7 @@ void Ctx::prof_end(int idx, double bytes, double flops) {
     r.flops = flops;
 }
 
-// Time the candidate block widths on up to 128 instances of the class (writing into their own
+// Time the candidate block widths on up to 512 instances of the class (writing into their own
 // outputs, which the full run then overwrites) and keep the fastest; cached per context. The sample
 // is large enough to fill the GPU with (matrix, block pair) tasks, so the timing reflects the
 // throughput regime of a large batch rather than the latency of a few matrices.
@@ -138,7 +138,7 @@ int tune_block_width(Ctx *c, int dtype, int M, int N, const std::vector<int> &cl
         *bw = it->second;
         return BSVD_OK;
     }
-    std::vector<int> sample(cls.begin(), cls.begin() + std::min<size_t>(cls.size(), 128));
+    std::vector<int> sample(cls.begin(), cls.begin() + std::min<size_t>(cls.size(), 512));
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return c->fail(BSVD_EHIP, "hipEventCreate");
