@@ -178,6 +178,169 @@ __global__ __launch_bounds__(256) void jacobi_lds_kernel(const SvdDesc *__restri
     }
 }
 
+// Square FP64 working matrices of 65..128 columns (the R_B factors of wide randomized-SVD bases,
+// rotated by rows: trans = 1): the working matrix alone fills the LDS (128 x 129 doubles), so V
+// lives in global memory -- in the caller's left-factor output D.V, used as scratch (L2-resident,
+// 128 KB per matrix) and overwritten with the normalised columns at the end, after the sorted V has
+// been copied to D.U. 512 threads: LPP = 8 lanes per pair for the 64 pairs of a step, each lane
+// holding rows l, l + 8, ... of both columns. Otherwise as jacobi_lds_kernel.
+__global__ __launch_bounds__(512) void jacobi_lds_wide_kernel(const SvdDesc *__restrict__ descs,
+                                                              const int *__restrict__ list, double tol,
+                                                              int max_sweeps, int *__restrict__ sweeps_out,
+                                                              int *__restrict__ info_out) {
+    constexpr int NT = 512;
+    constexpr int NMAX = 128;
+    constexpr int LPP = 8;
+    constexpr int RPL = NMAX / LPP;  // 16 rows per lane
+    constexpr int LDA = NMAX + 1;
+    extern __shared__ unsigned char smem_raw[];
+    double *sA = reinterpret_cast<double *>(smem_raw);
+    __shared__ double snorm[NMAX];
+
+    const int inst = list[blockIdx.x];
+    const SvdDesc D = descs[inst];
+    const int t = threadIdx.x;
+    const int N = D.N;  // square: M == N <= 128
+    const int NP = (N + 1) & ~1;
+    const double *Ap = static_cast<const double *>(D.A);
+    double *Vg = static_cast<double *>(D.V);  // V accumulator (scratch), N x N, ld D.ldv
+    const int ldv = D.ldv;
+
+    int nonfinite = 0;
+    for (int idx = t; idx < LDA * NMAX; idx += NT) {
+        const int c = idx / LDA, r = idx - c * LDA;
+        double x = 0.0;
+        if (c < N && r < N) x = Ap[c + (size_t)r * D.lda];  // rows of the stored matrix
+        if (!__builtin_isfinite(x)) nonfinite = 1;
+        sA[idx] = x;
+    }
+    for (int idx = t; idx < N * N; idx += NT) {
+        const int c = idx / N, r = idx - c * N;
+        Vg[r + (size_t)c * ldv] = (r == c) ? 1.0 : 0.0;
+    }
+    const int bad = __syncthreads_or(nonfinite);
+
+    const int g = t / LPP;
+    const int l = t - g * LPP;
+    int sweeps = 0;
+    bool converged = false;
+    if (!bad) {
+        for (int sw = 0; sw < max_sweeps; ++sw) {
+            int rotated = 0;
+            for (int s = 0; s < NP - 1; ++s) {
+                int p, q;
+                if (g == 0) {
+                    p = s;
+                    q = NP - 1;
+                } else {
+                    const int L = NP - 1;
+                    p = (s + g) % L;
+                    q = ((s - g) % L + L) % L;
+                }
+                const int i = p < q ? p : q;
+                const int j = p < q ? q : p;
+                const bool live = g < NP / 2;
+                double alpha = 0.0, beta = 0.0, gam = 0.0;
+                double ai[RPL], aj[RPL];
+#pragma unroll
+                for (int k = 0; k < RPL; ++k) {
+                    const int r = l + LPP * k;
+                    ai[k] = (live && r < N) ? sA[r + i * LDA] : 0.0;
+                    aj[k] = (live && r < N) ? sA[r + j * LDA] : 0.0;
+                    alpha = fma(ai[k], ai[k], alpha);
+                    beta = fma(aj[k], aj[k], beta);
+                    gam = fma(ai[k], aj[k], gam);
+                }
+                alpha = grp_sum<LPP>(alpha);
+                beta = grp_sum<LPP>(beta);
+                gam = grp_sum<LPP>(gam);
+                const bool rot = live && alpha > 0.0 && beta > 0.0 && fabs(gam) > tol * sqrt(alpha * beta);
+                if (rot) {
+                    double c, sn;
+                    jacobi_rot(alpha, beta, gam, c, sn);
+#pragma unroll
+                    for (int k = 0; k < RPL; ++k) {
+                        const int r = l + LPP * k;
+                        if (r < N) {
+                            sA[r + i * LDA] = c * ai[k] - sn * aj[k];
+                            sA[r + j * LDA] = sn * ai[k] + c * aj[k];
+                            double *vi = Vg + r + (size_t)i * ldv;
+                            double *vj = Vg + r + (size_t)j * ldv;
+                            const double a = *vi, b = *vj;
+                            *vi = c * a - sn * b;
+                            *vj = sn * a + c * b;
+                        }
+                    }
+                    rotated = 1;
+                }
+                __syncthreads();
+            }
+            sweeps = sw + 1;
+            if (!__syncthreads_or(rotated)) {
+                converged = true;
+                break;
+            }
+        }
+    }
+
+    for (int c = t / 4; c < NMAX; c += NT / 4) {
+        const int part = t & 3;
+        double s = 0.0;
+        for (int r = part; r < N; r += 4) s = fma(sA[r + c * LDA], sA[r + c * LDA], s);
+        s += __shfl_xor(s, 1, 64);
+        s += __shfl_xor(s, 2, 64);
+        if (part == 0) snorm[c] = sqrt(s);
+    }
+    __syncthreads();
+    double *S = static_cast<double *>(D.S);
+    if (bad) {
+        for (int c = t; c < N; c += NT) S[c] = __builtin_nan("");
+    } else {
+        double *Rf = static_cast<double *>(D.U);
+        const int ldr = D.ldu;
+        // sorted V (the rotations) to D.U first, then the normalised columns over the scratch in D.V
+        for (int c = t / 4; c < N; c += NT / 4) {
+            const int part = t & 3;
+            const double sc = snorm[c];
+            int rank = 0;
+            for (int q = 0; q < N; ++q) {
+                const double sq = snorm[q];
+                rank += (sq > sc || (sq == sc && q < c)) ? 1 : 0;
+            }
+            if (part == 0) S[rank] = sc;
+            for (int r = part; r < N; r += 4) Rf[r + (size_t)rank * ldr] = Vg[r + (size_t)c * ldv];
+        }
+        __syncthreads();
+        for (int c = t / 4; c < N; c += NT / 4) {
+            const int part = t & 3;
+            const double sc = snorm[c];
+            int rank = 0;
+            for (int q = 0; q < N; ++q) {
+                const double sq = snorm[q];
+                rank += (sq > sc || (sq == sc && q < c)) ? 1 : 0;
+            }
+            const double inv = sc > 0.0 ? 1.0 / sc : 0.0;
+            for (int r = part; r < N; r += 4) Vg[r + (size_t)rank * ldv] = sA[r + c * LDA] * inv;
+        }
+    }
+    if (t == 0) {
+        if (info_out) info_out[inst] = bad ? INFO_NONFINITE : (converged ? INFO_OK : INFO_SWEEPS);
+        if (sweeps_out) sweeps_out[inst] = bad ? 0 : sweeps;
+    }
+}
+
+hipError_t launch_jacobi_lds_wide(const SvdDesc *d, const int *list, int count, double tol, int max_sweeps,
+                                  int *sweeps, int *info, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    const size_t bytes = sizeof(double) * (size_t)129 * 128;
+    hipError_t e = hipFuncSetAttribute((const void *)jacobi_lds_wide_kernel,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(jacobi_lds_wide_kernel, dim3(count), dim3(512), bytes, st, d, list, tol, max_sweeps, sweeps,
+                       info);
+    return hipGetLastError();
+}
+
 bool jacobi_lds_supported(int dtype, int M, int N, int *mmax, int *nmax) {
     int NMAXv = 8;
     while (NMAXv < N) NMAXv <<= 1;

@@ -52,6 +52,7 @@ constexpr int CAP_OVER = 32;  // basis columns allowed beyond max_rank
 constexpr int PANEL = 64;     // widest matrix of the one-kernel QR / small Jacobi paths
 constexpr int GROW_BLK = 8;
 constexpr int BLOCK_W = 16;   // block width of the block Jacobi on R_B if the tuner finds none
+constexpr int WIDE_LDS = 128; // widest R_B for the LDS-resident Jacobi with V in global memory
 constexpr double SAFETY = 2.0;
 constexpr size_t WS_BUDGET = (size_t)96 << 30;  // workspace bound of one sub-batch
 
@@ -837,7 +838,8 @@ static int rsvd_range(Ctx *c, int inst_base, int batch, const int *m, const int 
         if ((rc = new_packer(p))) return rc;
         std::vector<QrDesc> qv;
         std::map<JKey, std::vector<int>> jb;
-        std::vector<int> blk_pos;  // positions (in `finished`) of the bases wider than one panel
+        std::vector<int> blk_pos;   // positions (in `finished`) of bases wider than 128 columns
+        std::vector<int> wide_pos;  // positions of bases of 65..128 columns
         SvdDesc *dsd;
         SvdDesc *hsd = p.put<SvdDesc>(F, &dsd);
         int *dl;
@@ -849,8 +851,15 @@ static int rsvd_range(Ctx *c, int inst_base, int batch, const int *m, const int 
             hl[i] = b;
             SvdDesc &d = hsd[i];
             std::memset(&d, 0, sizeof d);
-            if (q.ell > PANEL) {
+            if (q.ell > WIDE_LDS) {
                 blk_pos.push_back(i);
+                continue;
+            }
+            if (q.ell > PANEL) {
+                // R_B from the panel factorisation; one-sided Jacobi on its rows, V kept in U_R
+                d.A = dptr(q.oRB); d.m = q.ell; d.n = q.ell; d.lda = q.cap; d.trans = 1; d.M = q.ell; d.N = q.ell;
+                d.S = dptr(q.oSig); d.U = dptr(q.oVR); d.ldu = q.cap; d.V = dptr(q.oUR); d.ldv = q.cap;
+                wide_pos.push_back(i);
                 continue;
             }
             qv.push_back(qrdesc(dptr(q.oY), q.n, q.ell, q.n, dptr(q.oQB), q.n, dptr(q.oRB), q.cap));
@@ -870,6 +879,12 @@ static int rsvd_range(Ctx *c, int inst_base, int batch, const int *m, const int 
             if (!hjl) return commit(p);
             std::copy(kv.second.begin(), kv.second.end(), hjl);
             jl.push_back({kv.first, {djl, (int)kv.second.size()}});
+        }
+        int *dwl = nullptr;
+        if (!wide_pos.empty()) {
+            int *hwl = p.put<int>(wide_pos.size(), &dwl);
+            if (!hwl) return commit(p);
+            std::copy(wide_pos.begin(), wide_pos.end(), hwl);
         }
         QrDesc *dq;
         std::vector<QLaunch> ql;
@@ -898,6 +913,18 @@ static int rsvd_range(Ctx *c, int inst_base, int batch, const int *m, const int 
             if (e != hipSuccess) return c->hip_fail(e, "jacobi launch");
             c->prof_end(pi, jbytes[L.first], 0.0);
             if (pi >= 0) jrec.push_back({pi, &jb[L.first]});
+        }
+        if (!wide_pos.empty()) {
+            double by = 0.0;
+            for (int i : wide_pos) {
+                const double l = I[finished[i]].ell;
+                by += 8.0 * (3.0 * l * l + l);
+            }
+            pi = c->prof ? c->prof_begin(BSVD_STAGE_JACOBI, "jacobi_lds_wide_kernel") : -1;
+            e = launch_jacobi_lds_wide(dsd, dwl, (int)wide_pos.size(), 1e-15, 60, djsweeps, djinfo, c->stream);
+            if (e != hipSuccess) return c->hip_fail(e, "wide jacobi launch");
+            c->prof_end(pi, by, 0.0);
+            if (pi >= 0) jrec.push_back({pi, &wide_pos});
         }
         if (!blk_pos.empty()) {
             // block Jacobi on the columns of R_B (in the auxiliary workspace): left vectors -> V_R,
