@@ -179,32 +179,37 @@ __global__ __launch_bounds__(256) void jacobi_lds_kernel(const SvdDesc *__restri
 }
 
 // Square FP64 working matrices of 65..128 columns (the R_B factors of wide randomized-SVD bases,
-// rotated by rows: trans = 1): the working matrix alone fills the LDS (128 x 129 doubles), so V
-// lives in global memory -- in the caller's left-factor output D.V, used as scratch (L2-resident,
-// 128 KB per matrix) and overwritten with the normalised columns at the end, after the sorted V has
-// been copied to D.U. 512 threads: LPP = 8 lanes per pair for the 64 pairs of a step, each lane
-// holding rows l, l + 8, ... of both columns. Otherwise as jacobi_lds_kernel.
+// rotated by rows: trans = 1). Up to 96 columns the working matrix and V both fit the LDS
+// (2 x 97 x 96 doubles); beyond, the working matrix alone fills it (128 x 129 doubles) and V lives in
+// global memory -- in the caller's left-factor output D.V, used as scratch (L2-resident, 128 KB per
+// matrix) and overwritten with the normalised columns at the end, after the sorted V has been copied
+// to D.U. The global V rows of a step are loaded at the start of the step, so their latency overlaps
+// the Gram sums and reductions. 512 threads: LPP = 8 lanes per pair, each lane holding rows
+// l, l + 8, ... of both columns. Otherwise as jacobi_lds_kernel.
+template <int NMAX, bool VLDS>
 __global__ __launch_bounds__(512) void jacobi_lds_wide_kernel(const SvdDesc *__restrict__ descs,
                                                               const int *__restrict__ list, double tol,
                                                               int max_sweeps, int *__restrict__ sweeps_out,
                                                               int *__restrict__ info_out) {
     constexpr int NT = 512;
-    constexpr int NMAX = 128;
     constexpr int LPP = 8;
-    constexpr int RPL = NMAX / LPP;  // 16 rows per lane
+    constexpr int RPL = NMAX / LPP;
     constexpr int LDA = NMAX + 1;
     extern __shared__ unsigned char smem_raw[];
     double *sA = reinterpret_cast<double *>(smem_raw);
+    double *sV = sA + (size_t)LDA * NMAX;  // used when VLDS
     __shared__ double snorm[NMAX];
 
     const int inst = list[blockIdx.x];
     const SvdDesc D = descs[inst];
     const int t = threadIdx.x;
-    const int N = D.N;  // square: M == N <= 128
+    const int N = D.N;  // square: M == N <= NMAX
     const int NP = (N + 1) & ~1;
     const double *Ap = static_cast<const double *>(D.A);
-    double *Vg = static_cast<double *>(D.V);  // V accumulator (scratch), N x N, ld D.ldv
+    double *Vg = static_cast<double *>(D.V);  // global V accumulator (scratch) when !VLDS; ld D.ldv
     const int ldv = D.ldv;
+    double *Vb = VLDS ? sV : Vg;
+    const int ldV = VLDS ? LDA : ldv;
 
     int nonfinite = 0;
     for (int idx = t; idx < LDA * NMAX; idx += NT) {
@@ -216,7 +221,7 @@ __global__ __launch_bounds__(512) void jacobi_lds_wide_kernel(const SvdDesc *__r
     }
     for (int idx = t; idx < N * N; idx += NT) {
         const int c = idx / N, r = idx - c * N;
-        Vg[r + (size_t)c * ldv] = (r == c) ? 1.0 : 0.0;
+        Vb[r + (size_t)c * ldV] = (r == c) ? 1.0 : 0.0;
     }
     const int bad = __syncthreads_or(nonfinite);
 
@@ -240,6 +245,15 @@ __global__ __launch_bounds__(512) void jacobi_lds_wide_kernel(const SvdDesc *__r
                 const int i = p < q ? p : q;
                 const int j = p < q ? q : p;
                 const bool live = g < NP / 2;
+                // V rows first (global: in flight while the Gram entries are formed)
+                double vi[RPL], vj[RPL];
+#pragma unroll
+                for (int k = 0; k < RPL; ++k) {
+                    const int r = l + LPP * k;
+                    const bool ok = live && r < N && j < N;
+                    vi[k] = ok ? Vb[r + (size_t)i * ldV] : 0.0;
+                    vj[k] = ok ? Vb[r + (size_t)j * ldV] : 0.0;
+                }
                 double alpha = 0.0, beta = 0.0, gam = 0.0;
                 double ai[RPL], aj[RPL];
 #pragma unroll
@@ -264,11 +278,8 @@ __global__ __launch_bounds__(512) void jacobi_lds_wide_kernel(const SvdDesc *__r
                         if (r < N) {
                             sA[r + i * LDA] = c * ai[k] - sn * aj[k];
                             sA[r + j * LDA] = sn * ai[k] + c * aj[k];
-                            double *vi = Vg + r + (size_t)i * ldv;
-                            double *vj = Vg + r + (size_t)j * ldv;
-                            const double a = *vi, b = *vj;
-                            *vi = c * a - sn * b;
-                            *vj = sn * a + c * b;
+                            Vb[r + (size_t)i * ldV] = c * vi[k] - sn * vj[k];
+                            Vb[r + (size_t)j * ldV] = sn * vi[k] + c * vj[k];
                         }
                     }
                     rotated = 1;
@@ -298,7 +309,8 @@ __global__ __launch_bounds__(512) void jacobi_lds_wide_kernel(const SvdDesc *__r
     } else {
         double *Rf = static_cast<double *>(D.U);
         const int ldr = D.ldu;
-        // sorted V (the rotations) to D.U first, then the normalised columns over the scratch in D.V
+        // sorted V (the rotations) to D.U first, then the normalised columns to D.V (which held V
+        // when it lives in global memory)
         for (int c = t / 4; c < N; c += NT / 4) {
             const int part = t & 3;
             const double sc = snorm[c];
@@ -308,7 +320,7 @@ __global__ __launch_bounds__(512) void jacobi_lds_wide_kernel(const SvdDesc *__r
                 rank += (sq > sc || (sq == sc && q < c)) ? 1 : 0;
             }
             if (part == 0) S[rank] = sc;
-            for (int r = part; r < N; r += 4) Rf[r + (size_t)rank * ldr] = Vg[r + (size_t)c * ldv];
+            for (int r = part; r < N; r += 4) Rf[r + (size_t)rank * ldr] = Vb[r + (size_t)c * ldV];
         }
         __syncthreads();
         for (int c = t / 4; c < N; c += NT / 4) {
@@ -329,16 +341,23 @@ __global__ __launch_bounds__(512) void jacobi_lds_wide_kernel(const SvdDesc *__r
     }
 }
 
-hipError_t launch_jacobi_lds_wide(const SvdDesc *d, const int *list, int count, double tol, int max_sweeps,
+template <int NMAX, bool VLDS>
+static hipError_t lds_wide_one(const SvdDesc *d, const int *list, int count, double tol, int max_sweeps, int *sweeps,
+                               int *info, hipStream_t st) {
+    const size_t bytes = sizeof(double) * (size_t)(NMAX + 1) * NMAX * (VLDS ? 2 : 1);
+    auto kern = jacobi_lds_wide_kernel<NMAX, VLDS>;
+    hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3(count), dim3(512), bytes, st, d, list, tol, max_sweeps, sweeps, info);
+    return hipGetLastError();
+}
+
+hipError_t launch_jacobi_lds_wide(int nmax, const SvdDesc *d, const int *list, int count, double tol, int max_sweeps,
                                   int *sweeps, int *info, hipStream_t st) {
     if (count <= 0) return hipSuccess;
-    const size_t bytes = sizeof(double) * (size_t)129 * 128;
-    hipError_t e = hipFuncSetAttribute((const void *)jacobi_lds_wide_kernel,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(jacobi_lds_wide_kernel, dim3(count), dim3(512), bytes, st, d, list, tol, max_sweeps, sweeps,
-                       info);
-    return hipGetLastError();
+    if (nmax == 96) return lds_wide_one<96, true>(d, list, count, tol, max_sweeps, sweeps, info, st);
+    if (nmax == 128) return lds_wide_one<128, false>(d, list, count, tol, max_sweeps, sweeps, info, st);
+    return hipErrorInvalidValue;
 }
 
 bool jacobi_lds_supported(int dtype, int M, int N, int *mmax, int *nmax) {

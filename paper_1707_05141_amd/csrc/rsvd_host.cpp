@@ -880,11 +880,16 @@ static int rsvd_range(Ctx *c, int inst_base, int batch, const int *m, const int 
             std::copy(kv.second.begin(), kv.second.end(), hjl);
             jl.push_back({kv.first, {djl, (int)kv.second.size()}});
         }
-        int *dwl = nullptr;
-        if (!wide_pos.empty()) {
-            int *hwl = p.put<int>(wide_pos.size(), &dwl);
+        // 65..96 columns: V in LDS; 97..128: V in global memory
+        std::vector<int> wide_lo, wide_hi;
+        for (int i : wide_pos) (I[finished[i]].ell <= 96 ? wide_lo : wide_hi).push_back(i);
+        int *dwl_lo = nullptr, *dwl_hi = nullptr;
+        for (int h = 0; h < 2; ++h) {
+            const std::vector<int> &v = h ? wide_hi : wide_lo;
+            if (v.empty()) continue;
+            int *hwl = p.put<int>(v.size(), h ? &dwl_hi : &dwl_lo);
             if (!hwl) return commit(p);
-            std::copy(wide_pos.begin(), wide_pos.end(), hwl);
+            std::copy(v.begin(), v.end(), hwl);
         }
         QrDesc *dq;
         std::vector<QLaunch> ql;
@@ -914,17 +919,22 @@ static int rsvd_range(Ctx *c, int inst_base, int batch, const int *m, const int 
             c->prof_end(pi, jbytes[L.first], 0.0);
             if (pi >= 0) jrec.push_back({pi, &jb[L.first]});
         }
-        if (!wide_pos.empty()) {
+        for (int h = 0; h < 2; ++h) {
+            const std::vector<int> &v = h ? wide_hi : wide_lo;
+            if (v.empty()) continue;
             double by = 0.0;
-            for (int i : wide_pos) {
+            for (int i : v) {
                 const double l = I[finished[i]].ell;
                 by += 8.0 * (3.0 * l * l + l);
             }
-            pi = c->prof ? c->prof_begin(BSVD_STAGE_JACOBI, "jacobi_lds_wide_kernel") : -1;
-            e = launch_jacobi_lds_wide(dsd, dwl, (int)wide_pos.size(), 1e-15, 60, djsweeps, djinfo, c->stream);
+            pi = c->prof ? c->prof_begin(BSVD_STAGE_JACOBI, h ? "jacobi_lds_wide_kernel<128, false>"
+                                                               : "jacobi_lds_wide_kernel<96, true>")
+                         : -1;
+            e = launch_jacobi_lds_wide(h ? 128 : 96, dsd, h ? dwl_hi : dwl_lo, (int)v.size(), 1e-15, 60, djsweeps,
+                                       djinfo, c->stream);
             if (e != hipSuccess) return c->hip_fail(e, "wide jacobi launch");
             c->prof_end(pi, by, 0.0);
-            if (pi >= 0) jrec.push_back({pi, &wide_pos});
+            if (pi >= 0) jrec.push_back({pi, &v});
         }
         if (!blk_pos.empty()) {
             // block Jacobi on the columns of R_B (in the auxiliary workspace): left vectors -> V_R,
