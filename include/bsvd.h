@@ -252,7 +252,10 @@ int batched_rsvd(bsvd_ctx *ctx, int batch, const int *m, const int *n, const voi
  * bsvd_rank_features   DEVICE float[batch][16] features of each block: a probe sketch
  *                      Y = A Omega_p with 16 Gaussian columns (counter columns 2^20 ..), R = qr(Y),
  *                      f0 = log2(m)/9, f1 = log2(n)/9, f(1+i) = max(log10(|R_ii|/|R_00|), -20)/16 for
- *                      i = 1..14 (-20/16 beyond min(16, m, n) columns). Shapes as batched_rsvd.
+ *                      i = 1..13 (-20/16 beyond min(16, m, n) columns), f15 = log2(k ||A||_F^2 / s1^2)/8
+ *                      with k = min(16, m, n) and s1 the estimate of sigma_max(R) after 64 power steps
+ *                      on R^T R from (1, ..., 1)/sqrt(k) (a stable-rank feature that keeps resolving
+ *                      slowly decaying spectra). Shapes as batched_rsvd.
  * bsvd_rank_model_init     He-uniform weights, zero biases, Adam state reset (seeded)
  * bsvd_rank_model_set/get  parameters from / to a HOST float[5313]; margin added to 16 * prediction
  * bsvd_rank_model_save/load  binary file: "BSVDMLP1", int 5313, float margin, 5313 floats

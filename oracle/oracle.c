@@ -600,8 +600,9 @@ double oracle_mlp_loss_grad(int N, const double *p, const double *X, const doubl
 /* Probe features of a block (inputs of the rank-prediction network): the probe sketch          */
 /* Y = A Omega_p with kp = min(16, m, n) Gaussian columns at counter columns 2^20 .. 2^20+kp-1,  */
 /* R = qr(Y) (Householder, above), and                                                          */
-/*   f0 = log2(m)/9, f1 = log2(n)/9, f(1+i) = max(log10(|R_ii|/|R_00|), -20)/16, i = 1..14,     */
-/* with -20/16 where i >= kp or R_00 = 0.                                                        */
+/*   f0 = log2(m)/9, f1 = log2(n)/9, f(1+i) = max(log10(|R_ii|/|R_00|), -20)/16, i = 1..13,     */
+/* with -20/16 where i >= kp or R_00 = 0, and f15 = log2(kp ||A||_F^2 / s1^2)/8 with s1 the     */
+/* 64-step power-iteration estimate of sigma_max(R) (0 if ||A||_F or s1 is 0).                  */
 /* ------------------------------------------------------------------------------------------ */
 void oracle_features(int m, int n, const double *A, int lda, uint64_t seed, uint32_t inst, double *f) {
     int kp = 16;
@@ -614,7 +615,7 @@ void oracle_features(int m, int n, const double *A, int lda, uint64_t seed, uint
     f[0] = log2((double)m) / 9.0;
     f[1] = log2((double)n) / 9.0;
     double r0 = fabs(R[0]);
-    for (int i = 1; i < 15; ++i) {
+    for (int i = 1; i < 14; ++i) {
         double v = -20.0;
         if (i < kp && r0 > 0.0) {
             double ri = fabs(R[i + (size_t)i * kp]);
@@ -623,6 +624,35 @@ void oracle_features(int m, int n, const double *A, int lda, uint64_t seed, uint
         }
         f[1 + i] = v / 16.0;
     }
+    /* stable-rank feature: kp ||A||_F^2 / s1^2, s1 = ||R v|| after 64 power steps on R^T R from
+     * v = (1, ..., 1) / sqrt(kp) */
+    double a2 = frob2(m, n, A, lda);
+    double v[16], w[16];
+    for (int i = 0; i < kp; ++i) v[i] = 1.0 / sqrt((double)kp);
+    for (int it = 0; it < 64; ++it) {
+        for (int i = 0; i < kp; ++i) {
+            double s = 0.0;
+            for (int j = i; j < kp; ++j) s += R[i + (size_t)j * kp] * v[j];
+            w[i] = s;
+        }
+        double nz = 0.0;
+        for (int j = 0; j < kp; ++j) {
+            double s = 0.0;
+            for (int i = 0; i <= j; ++i) s += R[i + (size_t)j * kp] * w[i];
+            v[j] = s;
+            nz += s * s;
+        }
+        nz = sqrt(nz);
+        if (!(nz > 0.0)) break;
+        for (int j = 0; j < kp; ++j) v[j] /= nz;
+    }
+    double s1 = 0.0;
+    for (int i = 0; i < kp; ++i) {
+        double s = 0.0;
+        for (int j = i; j < kp; ++j) s += R[i + (size_t)j * kp] * v[j];
+        s1 += s * s;
+    }
+    f[15] = (a2 > 0.0 && s1 > 0.0) ? log2((double)kp * a2 / s1) / 8.0 : 0.0;
     free(Y);
     free(R);
 }

@@ -150,7 +150,10 @@ __global__ __launch_bounds__(256) void mlp_loss_kernel(int n, const float *__res
 
 // Probe features of block b from the k x k upper triangle R of its probe sketch (ld ldr):
 //   f0 = log2(m) / 9, f1 = log2(n) / 9,
-//   f(1 + i) = max(log10(|R_ii| / |R_00|), -20) / 16 for i = 1 .. 14 (-20/16 where i >= k or R_00 = 0).
+//   f(1 + i) = max(log10(|R_ii| / |R_00|), -20) / 16 for i = 1 .. 13 (-20/16 where i >= k or R_00 = 0),
+//   f15 = log2(k ||A||_F^2 / s1^2) / 8 with s1 = ||R v|| after 64 power steps on R^T R from
+//         v = (1, ..., 1) / sqrt(k) (0 if ||A||_F or s1 is 0): the stable rank of A seen through the
+//         probe, which keeps growing where the 16 diagonal entries no longer resolve a slow decay.
 __global__ void features_kernel(const FeatDesc *__restrict__ d, int count, float *__restrict__ feats) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= count) return;
@@ -159,7 +162,7 @@ __global__ void features_kernel(const FeatDesc *__restrict__ d, int count, float
     f[0] = (float)(log2((double)D.m) / 9.0);
     f[1] = (float)(log2((double)D.n) / 9.0);
     const double r0 = fabs(D.R[0]);
-    for (int i = 1; i < MLP_IN - 1; ++i) {
+    for (int i = 1; i < MLP_IN - 2; ++i) {
         double v = -20.0;
         if (i < D.k && r0 > 0.0) {
             const double ri = fabs(D.R[i + (size_t)i * D.ldr]);
@@ -167,6 +170,35 @@ __global__ void features_kernel(const FeatDesc *__restrict__ d, int count, float
         }
         f[1 + i] = (float)(v / 16.0);
     }
+    double a2 = 0.0;
+    for (int t = 0; t < D.ntile; ++t) a2 += D.xsq[2 * t] + D.xsq[2 * t + 1];
+    const int k = D.k;
+    double v[PROBE_COLS], w[PROBE_COLS];
+    for (int i = 0; i < k; ++i) v[i] = 1.0 / sqrt((double)k);
+    for (int it = 0; it < 64; ++it) {
+        for (int i = 0; i < k; ++i) {
+            double s = 0.0;
+            for (int j = i; j < k; ++j) s += D.R[i + (size_t)j * D.ldr] * v[j];
+            w[i] = s;
+        }
+        double nz = 0.0;
+        for (int j = 0; j < k; ++j) {
+            double s = 0.0;
+            for (int i = 0; i <= j; ++i) s += D.R[i + (size_t)j * D.ldr] * w[i];
+            v[j] = s;
+            nz += s * s;
+        }
+        nz = sqrt(nz);
+        if (!(nz > 0.0)) break;
+        for (int j = 0; j < k; ++j) v[j] /= nz;
+    }
+    double s1 = 0.0;
+    for (int i = 0; i < k; ++i) {
+        double s = 0.0;
+        for (int j = i; j < k; ++j) s += D.R[i + (size_t)j * D.ldr] * v[j];
+        s1 += s * s;
+    }
+    f[MLP_IN - 1] = (a2 > 0.0 && s1 > 0.0) ? (float)(log2((double)k * a2 / s1) / 8.0) : 0.0f;
 }
 
 __global__ void mlp_init_kernel(float *__restrict__ p, unsigned long long seed) {

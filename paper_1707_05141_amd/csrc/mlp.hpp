@@ -15,7 +15,8 @@ constexpr int PROBE_COL0 = 1 << 20;         // counter column of its first sampl
 // Features of one block from the R factor of its probe sketch.
 struct FeatDesc {
     const double *R;
-    int ldr, k, m, n, out;
+    const double *xsq;  // ||A||_F^2 as (hi, lo) pairs over ntile row tiles
+    int ldr, k, m, n, out, ntile;
 };
 
 hipError_t launch_mlp_forward(const float *params, int n, const float *X, float *y, hipStream_t st);

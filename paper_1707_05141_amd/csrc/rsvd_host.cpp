@@ -118,7 +118,7 @@ struct QLaunch {
 // PROBE_COL0), R = qr(Y), features from diag(R). Omp (n x kp row-major), Y (m x kp) and R (kp x kp,
 // ld ldr) are per-instance scratch given as device pointers. Enqueued on the context's stream.
 struct ProbeBufs {
-    double *Om, *Y, *R;
+    double *Om, *Y, *R, *xsq;  // xsq: (hi, lo) pairs per 64-row tile of A
     int ldr;
 };
 
@@ -146,7 +146,7 @@ static int probe_features(Ctx *c, int batch, const int *m, const int *n, const v
         hrd[b] = RngDesc{pb[b].Om, n[b], kp, PROBE_COL0, kp, inst_base + b, 0};
         for (int t = 0; t < cdiv(n[b] * kp, 256); ++t) rt.push_back(make_int2(b, t));
         MMDesc d;
-        d.X = static_cast<const double *>(A[b]); d.Y = pb[b].Om; d.C = pb[b].Y; d.xsq = nullptr; d.csq = nullptr;
+        d.X = static_cast<const double *>(A[b]); d.Y = pb[b].Om; d.C = pb[b].Y; d.xsq = pb[b].xsq; d.csq = nullptr;
         d.alpha = 1.0; d.beta = 0.0; d.M = m[b]; d.N = kp; d.K = n[b]; d.ldx = lda[b]; d.ldy = kp; d.ldc = m[b];
         d.ytrans = 1;
         sk[nmax_for(kp)].desc.push_back(d);
@@ -158,7 +158,7 @@ static int probe_features(Ctx *c, int batch, const int *m, const int *n, const v
         QKey k;
         if (!qr_config(m[b], kp, &k.nb, &k.seg, &k.kr)) return c->fail(BSVD_EUNSUP, "instance %d: probe QR", b);
         qbins[k].push_back(b);
-        hfd[b] = FeatDesc{pb[b].R, pb[b].ldr, kp, m[b], n[b], b};
+        hfd[b] = FeatDesc{pb[b].R, pb[b].xsq, pb[b].ldr, kp, m[b], n[b], b, cdiv(m[b], 64)};
         skcost[nmax_for(kp)].first += 8.0 * ((double)m[b] * n[b] + (double)(m[b] + n[b]) * kp);
         skcost[nmax_for(kp)].second += 2.0 * (double)m[b] * n[b] * kp;
     }
@@ -243,18 +243,20 @@ extern "C" int bsvd_rank_features(bsvd_ctx *ctx, int batch, const int *m, const 
     Arena ar;
     ar.off = dsz;
     std::vector<ProbeBufs> pb(batch);
-    std::vector<size_t> o(3 * (size_t)batch);
+    std::vector<size_t> o(4 * (size_t)batch);
     for (int b = 0; b < batch; ++b) {
-        o[3 * b] = ar.alloc(8 * (size_t)n[b] * PROBE_COLS);
-        o[3 * b + 1] = ar.alloc(8 * (size_t)m[b] * PROBE_COLS);
-        o[3 * b + 2] = ar.alloc(8 * (size_t)PROBE_COLS * PROBE_COLS);
+        o[4 * b] = ar.alloc(8 * (size_t)n[b] * PROBE_COLS);
+        o[4 * b + 1] = ar.alloc(8 * (size_t)m[b] * PROBE_COLS);
+        o[4 * b + 2] = ar.alloc(8 * (size_t)PROBE_COLS * PROBE_COLS);
+        o[4 * b + 3] = ar.alloc(16 * (size_t)cdiv(m[b], 64));
     }
     int rc = c->ensure_device(ar.off);
     if (rc) return rc;
     char *db = static_cast<char *>(c->dws);
     for (int b = 0; b < batch; ++b)
-        pb[b] = ProbeBufs{reinterpret_cast<double *>(db + o[3 * b]), reinterpret_cast<double *>(db + o[3 * b + 1]),
-                          reinterpret_cast<double *>(db + o[3 * b + 2]), PROBE_COLS};
+        pb[b] = ProbeBufs{reinterpret_cast<double *>(db + o[4 * b]), reinterpret_cast<double *>(db + o[4 * b + 1]),
+                          reinterpret_cast<double *>(db + o[4 * b + 2]), reinterpret_cast<double *>(db + o[4 * b + 3]),
+                          PROBE_COLS};
     return probe_features(c, batch, m, n, A, lda, pb, seed, feats, dsz, 0);
 }
 
@@ -612,7 +614,8 @@ static int rsvd_range(Ctx *c, int inst_base, int batch, const int *m, const int 
     // ---- learned initial sample count: probe features -> network -> ell0 ----------------------
     if (learned) {
         std::vector<ProbeBufs> pb(batch);
-        for (int b = 0; b < batch; ++b) pb[b] = ProbeBufs{dptr(I[b].oOm), dptr(I[b].oY), dptr(I[b].oRB), I[b].cap};
+        for (int b = 0; b < batch; ++b)
+            pb[b] = ProbeBufs{dptr(I[b].oOm), dptr(I[b].oY), dptr(I[b].oRB), dptr(I[b].oXsq), I[b].cap};
         float *dfeat = reinterpret_cast<float *>(db + oFeat);
         float *dpred = reinterpret_cast<float *>(db + oPred);
         int *dcap = reinterpret_cast<int *>(db + oCap);

@@ -398,3 +398,31 @@ def test_mlp_gradient_finite_differences():
         fd = (oracle.mlp_loss_grad(pp, X, y)[0] - oracle.mlp_loss_grad(pm, X, y)[0]) / (2 * h)
         assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(g[i])), (i, fd, g[i])
     np.testing.assert_allclose(loss, np.mean((oracle.mlp_forward(p, X) - y) ** 2))
+
+
+def test_features_against_numpy_probe():
+    """The probe features from their definition: the same Gaussian probe (oracle.omega at counter
+    column 2^20), numpy's QR, the log decay of |R_ii| and -- for a block with a clear top singular value,
+    where 64 power steps converge -- the stable-rank feature from numpy's largest singular value of R."""
+    rng = np.random.default_rng(4)
+    m, n, kp = 120, 90, 16
+    U = synth.haar(rng, m, n)
+    V = synth.haar(rng, n, n)
+    sig = np.concatenate([[10.0], np.exp(-np.arange(1, n) / 9.0)])
+    A = (U * sig) @ V.T
+    f = oracle.features(A, seed=17, inst=3)
+    Om = oracle.omega(17, 3, n, kp, 1 << 20)
+    R = np.linalg.qr(A @ Om, mode="r")
+    d = np.abs(np.diag(R))
+    assert abs(f[0] - np.log2(m) / 9) < 1e-15 and abs(f[1] - np.log2(n) / 9) < 1e-15
+    np.testing.assert_allclose(f[2:15], np.maximum(np.log10(d[1:14] / d[0]), -20) / 16, rtol=0, atol=1e-12)
+    s1 = np.linalg.svd(R, compute_uv=False)[0]
+    assert abs(f[15] - np.log2(kp * (A ** 2).sum() / s1 ** 2) / 8) < 1e-10
+
+
+def test_stable_rank_feature_grows_with_decay_width():
+    """Gaussian-decay blocks exp(-(i/w)^2): the stable rank ||A||_F^2 / sigma_1^2 grows like w, and so
+    does the feature; the 14 diagonal-decay features saturate for w beyond ~16."""
+    vals = [oracle.features(synth.gauss_decay(256, 256, w, 5, 0), seed=3, inst=0)[15] for w in (8, 16, 32, 64)]
+    assert all(b > a + 0.02 for a, b in zip(vals, vals[1:])), vals
+    assert vals[-1] - vals[0] > 0.1, vals
