@@ -50,6 +50,9 @@ namespace {
 constexpr int CAPMAX = 512;
 constexpr int CAP_OVER = 32;  // basis columns allowed beyond max_rank
 constexpr int PANEL = 64;     // widest matrix of the one-kernel QR / small Jacobi paths
+constexpr int PW = 32;        // panel width of the Gram-Schmidt orthonormalisation of wider bases
+                              // (Householder work grows with the square of the panel width, the
+                              // Gram-Schmidt products are GEMMs: narrower panels are cheaper)
 constexpr int GROW_BLK = 8;
 constexpr int BLOCK_W = 16;   // block width of the block Jacobi on R_B if the tuner finds none
 constexpr int WIDE_LDS = 128; // widest R_B for the LDS-resident Jacobi with V in global memory
@@ -283,7 +286,7 @@ static int rsvd_range(Ctx *c, int inst_base, int batch, const int *m, const int 
         q.ell0 = ell0 ? std::min(std::max(ell0[b], 0), q.cap) : 0;
         q.maxr = max_rank[b];
         q.f32 = mixed;
-        if (learned) q.ell0 = q.cap;  // the learned count is at most cap: size buffers for it
+        if (learned) q.ell0 = std::min(q.cap, PANEL);  // the learned first block is at most one panel
         const int bmax = std::max(std::max(GROW_BLK, q.ell0), PROBE_COLS);
         const int pan = cdiv(q.cap, PANEL);
         dsz += 4096 + 8 * (size_t)cdiv(q.n * bmax, 256) + (96 * pan + 192) * (size_t)cdiv(std::max(q.m, q.n), 64) +
@@ -508,7 +511,7 @@ static int rsvd_range(Ctx *c, int inst_base, int batch, const int *m, const int 
     };
 
     // Orthonormalisation of a matrix X (rows x cols, ld = rows) that is wider than one panel: panel 0
-    // by the Householder kernel; panel j > 0 (P, columns c0 = 64 j ...) by
+    // by the Householder kernel; panel j > 0 (P, columns c0 = PW j ...) by
     //   1-2. two classical Gram-Schmidt passes against Qo[:, :c0] (coefficients C1 + C2),
     //   3.   Householder QR of the residual: P = Qp Rp,
     //   4.   one more pass on the normalised Qp (D = Qo^T Qp, Qp -= Qo D) and its QR: Qp = Qp' R'.
@@ -518,7 +521,7 @@ static int rsvd_range(Ctx *c, int inst_base, int batch, const int *m, const int 
     // on vectors of norm one, removes that exactly. Then X = Qo R with, for the panel,
     //   R[0:c0, panel] = C1 + C2 + D Rp,   R[panel, panel] = R' Rp,   R[panel, 0:c0] = 0.
     // Writes Qo (rows x cols) and, when R is given, R (cols x cols, ld ldr); X is overwritten; T1,
-    // T2 (64 x 64 each) hold Rp and R'. One round per panel index, batched over the jobs.
+    // T2 (64 x 64 each, ld 64) hold Rp and R'. One round per panel index, batched over the jobs.
     struct PanelJob {
         int inst, rows, cols;
         double *X, *Qo, *R, *H, *T1, *T2;
@@ -526,7 +529,7 @@ static int rsvd_range(Ctx *c, int inst_base, int batch, const int *m, const int 
     };
     auto panel_qr = [&](const std::vector<PanelJob> &jobs) -> int {
         int maxp = 0;
-        for (const PanelJob &j : jobs) maxp = std::max(maxp, cdiv(j.cols, PANEL));
+        for (const PanelJob &j : jobs) maxp = std::max(maxp, cdiv(j.cols, PW));
         for (int pj = 0; pj < maxp; ++pj) {
             Packer p;
             int r2 = new_packer(p);
@@ -535,9 +538,9 @@ static int rsvd_range(Ctx *c, int inst_base, int batch, const int *m, const int 
             std::vector<QrDesc> qv1, qv2;
             std::vector<AddDesc> adds, copies;
             for (const PanelJob &j : jobs) {
-                const int c0 = pj * PANEL;
+                const int c0 = pj * PW;
                 if (c0 >= j.cols) continue;
-                const int pw = std::min(PANEL, j.cols - c0);
+                const int pw = std::min(PW, j.cols - c0);
                 double *P = j.X + (size_t)c0 * j.rows;
                 double *Qp = j.Qo + (size_t)c0 * j.rows;
                 if (pj == 0) {
@@ -632,10 +635,14 @@ static int rsvd_range(Ctx *c, int inst_base, int batch, const int *m, const int 
         c->prof_end(pi, 0.0, 0.0);
         if ((rc = readback(batch))) return rc;
         for (int b = 0; b < batch; ++b) {
-            I[b].ell0 = rbv()[b];
-            // a wide predicted basis means a slowly decaying spectrum, whose directions near the
-            // truncation sit at the FP32 noise level (about sqrt(n) u32 of ||A||_F): sample in FP64
-            if (I[b].ell0 > PANEL) I[b].f32 = false;
+            // A wide predicted basis means a slowly decaying spectrum: its directions near the
+            // truncation sit at the FP32 noise level (about sqrt(n) u32 of ||A||_F), so it samples in
+            // FP64; and its first block stops at one panel (64 columns): the rank predictions are
+            // least accurate there, and an overshoot costs the cube of the extra columns in the
+            // small SVD, while the growth that completes an undershoot costs a few 8-column rounds.
+            const int e0 = rbv()[b];
+            if (e0 > PANEL) I[b].f32 = false;
+            I[b].ell0 = std::min(e0, std::min(PANEL, I[b].cap));
         }
     }
 
@@ -1080,7 +1087,7 @@ extern "C" int batched_rsvd(bsvd_ctx *ctx, int batch, const int *m, const int *n
         int b1 = b0;
         while (b1 < batch) {
             const int cap = std::min(std::min(std::min(m[b1], n[b1]), CAPMAX), max_rank[b1] + CAP_OVER);
-            const int e0 = learned ? cap : (ell0 ? std::min(std::max(ell0[b1], 0), cap) : 0);
+            const int e0 = learned ? std::min(cap, PANEL) : (ell0 ? std::min(std::max(ell0[b1], 0), cap) : 0);
             const size_t need = inst_bytes(m[b1], n[b1], cap, std::max(std::max(GROW_BLK, e0), PROBE_COLS)) + 1024;
             if (b1 > b0 && acc + need > budget) break;
             acc += need;
