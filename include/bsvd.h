@@ -60,8 +60,10 @@ enum {
     BSVD_RSVD_FIXED = 1u << 0,  /* exactly ell0[b] samples, no adaptive growth (Algorithm 4 as printed) */
     BSVD_RSVD_LEARNED = 1u << 1, /* initial sample count from the context's rank model */
     BSVD_RSVD_MIXED = 1u << 2    /* sketch products Y = A Omega in FP32 (Omega drawn in FP32, A rounded
-                                    to FP32 on load, FP32 accumulation) while the samples are well above
-                                    FP32 rounding: an instance goes on in FP64 once the growth estimate
+                                    to FP32 on load, FP32 accumulation) for instances whose tolerance
+                                    is above 16 sqrt(cap n) u32 (u32 = 2^-24; a basis of FP32 samples
+                                    misses about sqrt(cap n) u32 ||A||_F of A, which only FP64 samples
+                                    repair); such an instance goes on in FP64 once the growth estimate
                                     is within 16 sqrt(n) u32 ||A||_F of the FP32 noise floor, after a
                                     failed exact check, and (with LEARNED) when the predicted basis is
                                     wider than 64 columns. The basis QR, the projection B = Q^T A, the

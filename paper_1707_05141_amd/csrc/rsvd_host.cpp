@@ -31,6 +31,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdlib>
 #include <cstring>
 #include <map>
@@ -285,7 +286,14 @@ static int rsvd_range(Ctx *c, int inst_base, int batch, const int *m, const int 
         q.ell = 0;
         q.ell0 = ell0 ? std::min(std::max(ell0[b], 0), q.cap) : 0;
         q.maxr = max_rank[b];
-        q.f32 = mixed;
+        // FP32 samples carry rounding noise of about sqrt(n) u32 ||A||_F each; a basis of up to cap
+        // such samples misses A-energy of about sqrt(cap n) u32 ||A||_F, which only more FP64 samples
+        // repair. So FP32 serves an instance only when that floor is well below its tolerance.
+        {
+            const double u32 = 5.9604644775390625e-08;
+            const double e_b = eps ? eps[b] : 1e-6;
+            q.f32 = mixed && e_b > 16.0 * std::sqrt((double)q.cap * (double)q.n) * u32;
+        }
         if (learned) q.ell0 = std::min(q.cap, PANEL);  // the learned first block is at most one panel
         const int bmax = std::max(std::max(GROW_BLK, q.ell0), PROBE_COLS);
         const int pan = cdiv(q.cap, PANEL);

@@ -282,3 +282,31 @@ def test_rsvd_split_into_sub_batches_is_bitwise_identical(monkeypatch):
     torch.cuda.synchronize()
     for key in ("S", "U", "V", "rank", "err_est", "info", "samples"):
         assert torch.equal(one[key], split[key]), key
+
+
+def test_rsvd_mixed_precision_active_at_loose_tolerance():
+    """At eps = 1e-3 the FP32 sketch floor (about sqrt(cap n) u32 = 1e-5 here) is far below the
+    tolerance, so the FP32 products are used (seen in the kernel profile); the FP64 check still holds
+    the error to eps, and the rank stays within [k*, k* + 3] (Eckart-Young lower bound)."""
+    eps = 1e-3
+    rng = np.random.default_rng(9)
+    shapes = [(int(rng.choice([64, 128, 256])), int(rng.choice([64, 128, 256]))) for _ in range(24)]
+    mats = _kernel_batch(shapes, seed=44)
+    buf, offs, m, n = P.pack_colmajor(mats)
+    P.profile_enable(True)
+    mixed = P.rsvd_packed(buf, offs, m, n, eps=eps, max_rank=64, seed=6, flags=_lib.RSVD_MIXED)
+    torch.cuda.synchronize()
+    kern = P.profile_kernels()
+    P.profile_read()
+    P.profile_enable(False)
+    assert any(k.startswith("gemm_nn_kernel<") and k.endswith(", float>") for k in kern), list(kern)
+    for b, A in enumerate(mats):
+        mm, nn = A.shape
+        S, U, V = _unpack(mixed, mm, nn, b)
+        rel = np.linalg.norm(A - (U * S) @ V.T) / np.linalg.norm(A)
+        assert rel <= eps, (b, rel)
+        sx = np.linalg.svd(A, compute_uv=False)
+        tail = np.sqrt(np.maximum(0.0, (sx ** 2).sum() - np.cumsum(np.concatenate([[0.0], sx ** 2]))))
+        k_star = int(np.argmax(tail <= eps * np.sqrt((sx ** 2).sum())))
+        assert k_star - (1 if _ambiguous(A, eps, k_star) else 0) <= len(S) <= k_star + 3, (b, len(S), k_star)
+        np.testing.assert_allclose(S, sx[:len(S)], rtol=0, atol=1e-5 * sx[0])
