@@ -209,11 +209,12 @@ def _orth_haar(G):
     return Q
 
 
-def mixed_blocks_packed(m, n, kinds, w, seed, device="cuda", chunk=256, progress=None):
+def mixed_blocks_packed(m, n, kinds, w, seed, device="cuda", chunk=64, progress=None):
     """The mixed batch packed column-major (256-byte aligned) on `device`. Kernel blocks as in
     kernel_blocks_packed; gauss_decay blocks U diag(exp(-(i/w)^2)) V^T with Haar U (m x k), V (n x k)
     (orthonormal factors of Gaussian matrices, see _orth_haar), drawn per chunk of `chunk` blocks of
-    one (m, n) class (chunks formed in order of w) from a generator seeded by (seed, m, n, chunk).
+    one (m, n) class (chunks formed in order of w) from a generator seeded by (seed, m, n, chunk);
+    chunks of 64 keep the batched LU of the triangular inverses within the BLAS workspace.
     Terms with exp(-(i/w)^2) < 1e-18 (i > 6.44 w) are left out: they change no entry of the block at
     FP64 resolution, and the first k columns of a Haar factor are themselves Haar, so
     k = min(m, n, ceil(6.44 w_max)) per chunk. `progress(text)` is called after each (m, n) class."""
