@@ -101,6 +101,29 @@ KERNEL_BOUND = (("gemm_nn_kernel", "hbm"), ("gemm_tn_kernel", "hbm"), ("bj_gram_
                 ("bj_apply_kernel", "mfma"), ("qr_kernel", "alu"), ("jacobi_", "alu"))
 
 
+def pmc_traffic(kernel):
+    """HBM bytes per launch of `kernel` from a committed PMC summary under profiles/ (a line
+    "traffic: kernel=... fetch_kib=... fetch_scale=... write_kib=... write_scale=... source=... sha1=..."),
+    or None if there is none or the kernel's source file has changed since the counters were taken."""
+    import glob
+    import hashlib
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        for line in open(path):
+            if not line.startswith("traffic: kernel="):
+                continue
+            fields = dict(kv.split("=", 1) for kv in line[len("traffic: "):].strip().split(" ") if "=" in kv)
+            # the kernel name contains ", " inside its template arguments: re-join what split broke
+            name = line[len("traffic: kernel="):].split(" fetch_kib=")[0]
+            if name != kernel:
+                continue
+            src = os.path.join(ROOT, fields["source"])
+            if not os.path.exists(src) or hashlib.sha1(open(src, "rb").read()).hexdigest() != fields["sha1"]:
+                return None
+            return 1024.0 * (float(fields["fetch_kib"]) * float(fields["fetch_scale"]) +
+                             float(fields["write_kib"]) * float(fields["write_scale"]))
+    return None
+
+
 def kernel_roofline(kern, steps):
     """Roofline entry of the kernel instantiation with the largest total time in the per-launch
     profile `kern` ({name: dict(ms, bytes, flops, launches)}), plus the top of the kernel table."""
@@ -118,9 +141,10 @@ def kernel_roofline(kern, steps):
         ach = per / (avg_ms * 1e-3) / 1e12
         peak = FP64_PEAK_TFLOPS if bound == "alu" else FP64_PEAK_TFLOPS
         unit = "TFLOP/s"
-    roof = dict(bound=bound, achieved=ach, peak=peak, unit=unit, frac=ach / peak, traffic=None, kernel=name,
+    roof = dict(bound=bound, achieved=ach, peak=peak, unit=unit, frac=ach / peak, traffic=pmc_traffic(name), kernel=name,
                 kernel_avg_ms=avg_ms, launches_per_step=k["launches"] / steps,
-                algorithmic_per_launch=per, algorithmic_unit="bytes" if bound == "hbm" else "flops")
+                algorithmic_per_launch=per, algorithmic_unit="bytes" if bound == "hbm" else "flops",
+                algorithmic_bytes_per_launch=k["bytes"] / k["launches"], traffic_unit="bytes per launch")
     table = [dict(kernel=n, stage=v["stage"], ms_per_step=v["ms"] / steps, launches_per_step=v["launches"] / steps,
                   avg_ms=v["ms"] / v["launches"]) for n, v in ranked[:10]]
     return roof, table
