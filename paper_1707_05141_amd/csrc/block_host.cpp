@@ -51,6 +51,10 @@ int block_jacobi_run(Ctx *c, int dtype, int w, const std::vector<int> &insts, co
     ar.off = dsz;
     const size_t oMats = ar.alloc(sizeof(BjMat) * (size_t)nm);
     const size_t oFlags = ar.alloc(sizeof(int) * (size_t)nm);
+    // rotated block pairs per (active matrix, step) of the last sweep; read back when profiling, so
+    // that each apply launch is credited with the pairs it rotated (converged pairs return early)
+    const int rot_ld = std::max(1, nbmax - 1);
+    const size_t oRot = ar.alloc(sizeof(int) * (size_t)nm * rot_ld);
     for (int i = 0; i < nm; ++i) {
         HM &h = hm[i];
         const int npairs = h.nb * (h.nb - 1) / 2;
@@ -65,11 +69,12 @@ int block_jacobi_run(Ctx *c, int dtype, int w, const std::vector<int> &insts, co
     if (rc) return rc;
     rc = c->ensure_host(std::max(dsz, sizeof(BjMat) * (size_t)nm));
     if (rc) return rc;
-    rc = c->ensure_readback(sizeof(int) * (size_t)nm);
+    rc = c->ensure_readback(sizeof(int) * (size_t)nm * (1 + rot_ld));
     if (rc) return rc;
     char *db = static_cast<char *>(c->dws);
     BjMat *dmats = reinterpret_cast<BjMat *>(db + oMats);
     int *dflags = reinterpret_cast<int *>(db + oFlags);
+    int *drot = reinterpret_cast<int *>(db + oRot);
     {
         BjMat *hmats = static_cast<BjMat *>(c->hws);
         for (int i = 0; i < nm; ++i) {
@@ -93,6 +98,7 @@ int block_jacobi_run(Ctx *c, int dtype, int w, const std::vector<int> &insts, co
             B.trans = m[b] < n[b] ? 1 : 0;
             B.inst = b;
             B.ntask_state = h.nb * (h.nb - 1) / 2;
+            B.nb = h.nb;
         }
         if ((rc = c->upload_to(oMats, sizeof(BjMat) * (size_t)nm))) return rc;
     }
@@ -107,7 +113,9 @@ int block_jacobi_run(Ctx *c, int dtype, int w, const std::vector<int> &insts, co
 
     std::vector<int> active(nm);
     for (int i = 0; i < nm; ++i) active[i] = i;
+    std::vector<int> app_rec(rot_ld, -1);
     for (int sw = 0; sw < max_sweeps && !active.empty(); ++sw) {
+        std::fill(app_rec.begin(), app_rec.end(), -1);
         for (int s = 0; s < nbmax - 1; ++s) {
             // tasks of this step
             if ((rc = c->ensure_host(dsz))) return rc;
@@ -195,6 +203,7 @@ int block_jacobi_run(Ctx *c, int dtype, int w, const std::vector<int> &insts, co
             e = launch_bj_apply(dtype, w, dmats, dt, (int)ntask, c->stream);
             if (e != hipSuccess) return c->hip_fail(e, "block apply launch");
             c->prof_end(pi, app_b, app_f);
+            app_rec[s] = pi;
         }
         // convergence of the sweep
         if ((rc = c->ensure_host(dsz))) return rc;
@@ -203,14 +212,36 @@ int block_jacobi_run(Ctx *c, int dtype, int w, const std::vector<int> &insts, co
         if ((rc = c->upload(sizeof(int) * active.size()))) return rc;
         const int *dl = reinterpret_cast<const int *>(db);
         pi = c->prof_begin(BSVD_STAGE_SMALL, "bj_sweep_kernel");
-        e = launch_bj_sweep(dmats, dl, (int)active.size(), tol, dflags, c->stream);
+        e = launch_bj_sweep(dmats, dl, (int)active.size(), tol, dflags, c->prof ? drot : nullptr, rot_ld, c->stream);
         if (e != hipSuccess) return c->hip_fail(e, "block sweep launch");
         c->prof_end(pi, 0.0, 0.0);
         e = hipMemcpyAsync(c->rb, dflags, sizeof(int) * active.size(), hipMemcpyDeviceToHost, c->stream);
         if (e != hipSuccess) return c->hip_fail(e, "hipMemcpyAsync(block flags)");
+        if (c->prof) {
+            e = hipMemcpyAsync(static_cast<int *>(c->rb) + nm, drot, sizeof(int) * active.size() * rot_ld,
+                               hipMemcpyDeviceToHost, c->stream);
+            if (e != hipSuccess) return c->hip_fail(e, "hipMemcpyAsync(block rotation counts)");
+        }
         e = hipStreamSynchronize(c->stream);
         if (e != hipSuccess) return c->hip_fail(e, "hipStreamSynchronize");
         const int *rb = static_cast<const int *>(c->rb);
+        if (c->prof) {
+            // credit each apply launch of the sweep with the block pairs it actually rotated
+            const int *rot = rb + nm;
+            for (int s = 0; s < rot_ld; ++s) {
+                if (app_rec[s] < 0) continue;
+                double by = 0.0, fl = 0.0;
+                for (size_t j = 0; j < active.size(); ++j) {
+                    const HM &h = hm[active[j]];
+                    if (s >= h.nb - 1) continue;
+                    const double cnt = rot[j * rot_ld + s];
+                    by += cnt * 2.0 * (double)esz * (h.M + h.NP) * K;
+                    fl += cnt * 2.0 * (h.M + h.NP) * (double)K * K;
+                }
+                c->recs[app_rec[s]].bytes = by;
+                c->recs[app_rec[s]].flops = fl;
+            }
+        }
         std::vector<int> still, done;
         for (size_t i = 0; i < active.size(); ++i) (rb[i] ? done : still).push_back(active[i]);
         if (!done.empty()) {

@@ -178,9 +178,10 @@ __global__ __launch_bounds__(256) void bj_apply_kernel(const BjMat *__restrict__
     }
 }
 
-// Per matrix: maximum pair measure of the sweep -> done flag.
+// Per matrix: maximum pair measure of the sweep -> done flag; optionally the number of rotated
+// pairs per round-robin step (pair slot s * nb/2 + g holds pair g of step s).
 __global__ void bj_sweep_kernel(BjMat *__restrict__ mats, const int *__restrict__ list, int count, double tol,
-                                int *__restrict__ flags) {
+                                int *__restrict__ flags, int *__restrict__ rot, int rot_ld) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= count) return;
     BjMat &B = mats[list[i]];
@@ -188,6 +189,14 @@ __global__ void bj_sweep_kernel(BjMat *__restrict__ mats, const int *__restrict_
     for (int s = 0; s < B.ntask_state; ++s) e = fmax(e, B.pair_state[2 * s]);
     B.sweeps += 1;
     flags[i] = e <= tol ? 1 : 0;
+    if (rot) {
+        const int hb = B.nb / 2;
+        for (int s = 0; s < B.nb - 1; ++s) {
+            int cnt = 0;
+            for (int g = 0; g < hb; ++g) cnt += B.pair_state[2 * (s * hb + g) + 1] != 0.0 ? 1 : 0;
+            rot[(size_t)i * rot_ld + s] = cnt;
+        }
+    }
 }
 
 // sigma = column norms, descending (stable); U = normalised columns of W, V = accumulated rotations.
@@ -291,9 +300,11 @@ hipError_t launch_bj_apply(int dtype, int w, const BjMat *mats, const BjTask *ta
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_bj_sweep(BjMat *mats, const int *list, int count, double tol, int *flags, hipStream_t st) {
+hipError_t launch_bj_sweep(BjMat *mats, const int *list, int count, double tol, int *flags, int *rot, int rot_ld,
+                           hipStream_t st) {
     if (count <= 0) return hipSuccess;
-    hipLaunchKernelGGL(bj_sweep_kernel, dim3((count + 255) / 256), dim3(256), 0, st, mats, list, count, tol, flags);
+    hipLaunchKernelGGL(bj_sweep_kernel, dim3((count + 255) / 256), dim3(256), 0, st, mats, list, count, tol, flags,
+                       rot, rot_ld);
     return hipGetLastError();
 }
 

@@ -125,13 +125,15 @@ void Ctx::prof_end(int idx, double bytes, double flops) {
     r.flops = flops;
 }
 
-// Time the candidate block widths on up to 512 instances of the class (writing into their own
-// outputs, which the full run then overwrites) and keep the fastest; cached per context. The sample
-// is large enough to fill the GPU with (matrix, block pair) tasks, so the timing reflects the
-// throughput regime of a large batch rather than the latency of a few matrices.
+// Time the candidate block widths (and the optional single-kernel path, width 0) on up to 512
+// instances of the class (writing into their own outputs, which the full run then overwrites) and
+// keep the fastest; cached per context. The sample is large enough to fill the GPU with (matrix,
+// block pair) tasks, so the timing reflects the throughput regime of a large batch rather than the
+// latency of a few matrices.
 int tune_block_width(Ctx *c, int dtype, int M, int N, const std::vector<int> &cls, const int *m, const int *n,
                      const void *const *A, const int *lda, void *const *S, void *const *U, const int *ldu,
-                     void *const *V, const int *ldv, double tol, int max_sweeps, int *bw, int kind) {
+                     void *const *V, const int *ldv, double tol, int max_sweeps, int *bw, int kind,
+                     const std::function<int(const std::vector<int> &)> *alt) {
     const auto key = std::make_tuple(kind, dtype, M, N);
     auto it = c->tune.find(key);
     if (it != c->tune.end()) {
@@ -147,10 +149,14 @@ int tune_block_width(Ctx *c, int dtype, int M, int N, const std::vector<int> &cl
     int best = 16;
     float best_t = -1.0f;
     std::vector<std::pair<int, float>> times;
-    for (int w : {8, 16, 32}) {
+    std::vector<int> cands;
+    if (alt) cands.push_back(0);
+    for (int w : {8, 16, 32}) cands.push_back(w);
+    for (int w : cands) {
         hipEventRecord(e0, c->stream);
-        int rc = block_jacobi_run(c, dtype, w, sample, m, n, A, lda, S, U, ldu, V, ldv, tol, max_sweeps, nullptr,
-                                  nullptr);
+        int rc = w == 0 ? (*alt)(sample)
+                        : block_jacobi_run(c, dtype, w, sample, m, n, A, lda, S, U, ldu, V, ldv, tol, max_sweeps,
+                                           nullptr, nullptr);
         if (rc) {
             c->prof = prof;
             hipEventDestroy(e0);

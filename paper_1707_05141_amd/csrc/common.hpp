@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <functional>
 #include <vector>
 
 namespace bsvd {
@@ -60,9 +61,13 @@ hipError_t launch_jacobi_lds_wide(int nmax, const SvdDesc *d, const int *list, i
 hipError_t launch_gemm_small(int dtype, const GemmDesc *d, const int *list, int count, hipStream_t st);
 
 struct Ctx;
+// Block width for a class of matrices, timed on up to 512 of them and cached per context under
+// (kind, dtype, M, N). When `alt` is given it is a further candidate, reported as width 0: it runs
+// the class sample on a single-kernel Jacobi path and returns a status code.
 int tune_block_width(Ctx *c, int dtype, int M, int N, const std::vector<int> &cls, const int *m, const int *n,
                      const void *const *A, const int *lda, void *const *S, void *const *U, const int *ldu,
-                     void *const *V, const int *ldv, double tol, int max_sweeps, int *bw, int kind = 0);
+                     void *const *V, const int *ldv, double tol, int max_sweeps, int *bw, int kind = 0,
+                     const std::function<int(const std::vector<int> &)> *alt = nullptr);
 int block_jacobi_run(Ctx *c, int dtype, int w, const std::vector<int> &insts, const int *m, const int *n,
                      const void *const *A, const int *lda, void *const *S, void *const *U, const int *ldu,
                      void *const *V, const int *ldv, double tol, int max_sweeps, int *sweeps, int *info);

@@ -341,6 +341,237 @@ __global__ __launch_bounds__(512) void jacobi_lds_wide_kernel(const SvdDesc *__r
     }
 }
 
+// Lane-quad exchange of a double: lane 4q + a receives the value of lane 4q + perm[a], perm given
+// as a DPP quad_perm control (two 32-bit DPP moves).
+template <int CTRL>
+__device__ __forceinline__ double quad_perm(double x) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+constexpr int QP_NEXT = 1 | (2 << 2) | (3 << 4) | (0 << 6);  // from lane a + 1 (mod 4)
+constexpr int QP_PREV = 3 | (0 << 2) | (1 << 4) | (2 << 6);  // from lane a - 1 (mod 4)
+constexpr int QP_L0 = 0;                                     // from lane 0 of the quad
+constexpr int QP_L3 = 3 | (3 << 2) | (3 << 4) | (3 << 6);    // from lane 3 of the quad
+
+// Square FP64 working matrices of 97..128 columns with the accumulated rotations V in registers.
+// The working matrix fills the LDS (128 x 129 doubles); V is distributed by rows: thread t holds row
+// r = t / 4 of V for the column pairs g = 4 k + (t % 4), k = 0..15, i.e. the two columns that pair g
+// rotates in the current round-robin step. Each step has two phases separated by one barrier:
+//   W phase: pair g (8 lanes, as in the other LDS kernels) forms its Gram entries from the LDS
+//            columns, derives the rotation, stores (c, s) in a double-buffered table and rotates its
+//            two LDS columns;
+//   V phase: every thread applies the 16 rotations of its pairs to its row of V, then passes the
+//            columns on to the threads that hold them in the next step. In the circle schedule the
+//            column a pair holds first moves to pair g - 1 and the second to pair g + 1 (pair 0 keeps
+//            the fixed last column, the first column of pair 0 becomes the second of pair 1, the
+//            second column of the last pair becomes its first), so every move stays inside a lane
+//            quad (DPP quad permutations) or shifts one register slot at the quad boundary.
+// V never leaves the registers until the sorted output is written, so no step waits on global
+// memory. Rotation rule, ordering, test and outputs are those of jacobi_lds_wide_kernel.
+__global__ __launch_bounds__(512) void jacobi_lds_vreg_kernel(const SvdDesc *__restrict__ descs,
+                                                               const int *__restrict__ list, double tol,
+                                                               int max_sweeps, int *__restrict__ sweeps_out,
+                                                               int *__restrict__ info_out) {
+    constexpr int NMAX = 128;
+    constexpr int NT = 512;
+    constexpr int LPP = 8;
+    constexpr int RPL = NMAX / LPP;
+    constexpr int LDA = NMAX + 1;
+    constexpr int SLOTS = NMAX / 2 / 4;  // pairs per V thread
+    extern __shared__ unsigned char smem_raw[];
+    double *sA = reinterpret_cast<double *>(smem_raw);
+    __shared__ double rot_c[2][NMAX / 2], rot_s[2][NMAX / 2];
+    __shared__ double snorm[NMAX];
+    __shared__ int srank[NMAX];
+
+    const int inst = list[blockIdx.x];
+    const SvdDesc D = descs[inst];
+    const int t = threadIdx.x;
+    const int N = D.N;  // square: M == N <= NMAX
+    const int NP = (N + 1) & ~1;
+    const int L = NP - 1;
+    const int G = NP / 2;
+    const double *Ap = static_cast<const double *>(D.A);
+
+    int nonfinite = 0;
+    for (int idx = t; idx < LDA * NMAX; idx += NT) {
+        const int c = idx / LDA, r = idx - c * LDA;
+        double x = 0.0;
+        if (c < N && r < N) x = Ap[c + (size_t)r * D.lda];  // rows of the stored matrix
+        if (!__builtin_isfinite(x)) nonfinite = 1;
+        sA[idx] = x;
+    }
+    const int bad = __syncthreads_or(nonfinite);
+
+    // W-phase role
+    const int g = t / LPP;
+    const int l = t - g * LPP;
+    // V-phase role: row vr, pairs 4 k + vp
+    const int vr = t >> 2;
+    const int vp = t & 3;
+    // columns held by pair gg at step s: first = s + gg, second = s - gg (mod L); pair 0: (s, L)
+    auto first_col = [&](int gg, int s) { return gg == 0 ? s : (s + gg) % L; };
+    auto second_col = [&](int gg, int s) { return gg == 0 ? L : ((s - gg) % L + L) % L; };
+    double vf[SLOTS], vs[SLOTS];  // V[vr, first / second column of pair 4 k + vp]
+    int cf[SLOTS], cs[SLOTS];     // those column indices at the current step
+#pragma unroll
+    for (int k = 0; k < SLOTS; ++k) {
+        const int gg = 4 * k + vp;
+        cf[k] = gg < G ? first_col(gg, 0) : 0;
+        cs[k] = gg < G ? second_col(gg, 0) : 0;
+        vf[k] = (gg < G && vr < N && cf[k] == vr) ? 1.0 : 0.0;
+        vs[k] = (gg < G && vr < N && cs[k] == vr) ? 1.0 : 0.0;
+    }
+    int sweeps = 0;
+    bool converged = false;
+    if (!bad) {
+        for (int sw = 0; sw < max_sweeps; ++sw) {
+            int rotated = 0;
+            for (int s = 0; s < L; ++s) {
+                const int buf = s & 1;
+                {
+                    const bool live = g < G;
+                    const int p = live ? first_col(g, s) : 0, q = live ? second_col(g, s) : 1;
+                    const int i = p < q ? p : q;
+                    const int j = p < q ? q : p;
+                    double alpha = 0.0, beta = 0.0, gam = 0.0;
+                    double ai[RPL], aj[RPL];
+#pragma unroll
+                    for (int k = 0; k < RPL; ++k) {
+                        const int r = l + LPP * k;
+                        ai[k] = (live && r < N) ? sA[r + i * LDA] : 0.0;
+                        aj[k] = (live && r < N) ? sA[r + j * LDA] : 0.0;
+                        alpha = fma(ai[k], ai[k], alpha);
+                        beta = fma(aj[k], aj[k], beta);
+                        gam = fma(ai[k], aj[k], gam);
+                    }
+                    alpha = grp_sum<LPP>(alpha);
+                    beta = grp_sum<LPP>(beta);
+                    gam = grp_sum<LPP>(gam);
+                    const bool rot = live && alpha > 0.0 && beta > 0.0 && fabs(gam) > tol * sqrt(alpha * beta);
+                    double c = 1.0, sn = 0.0;
+                    if (rot) {
+                        jacobi_rot(alpha, beta, gam, c, sn);
+#pragma unroll
+                        for (int k = 0; k < RPL; ++k) {
+                            const int r = l + LPP * k;
+                            if (r < N) {
+                                sA[r + i * LDA] = c * ai[k] - sn * aj[k];
+                                sA[r + j * LDA] = sn * ai[k] + c * aj[k];
+                            }
+                        }
+                        rotated = 1;
+                    }
+                    if (live && l == 0) {
+                        rot_c[buf][g] = c;
+                        rot_s[buf][g] = sn;
+                    }
+                }
+                __syncthreads();
+                // V phase: rotate the row, then move the columns to their holders at step s + 1
+#pragma unroll
+                for (int k = 0; k < SLOTS; ++k) {
+                    const int gg = 4 * k + vp;
+                    if (gg < G) {
+                        const double c = rot_c[buf][gg], sn = rot_s[buf][gg];
+                        const double a = vf[k], b = vs[k];
+                        if (cf[k] < cs[k]) {
+                            vf[k] = c * a - sn * b;
+                            vs[k] = sn * a + c * b;
+                        } else {
+                            vs[k] = c * b - sn * a;
+                            vf[k] = sn * b + c * a;
+                        }
+                    }
+                }
+                double nf[SLOTS], ns[SLOTS];
+#pragma unroll
+                for (int k = 0; k < SLOTS; ++k) {
+                    const int gg = 4 * k + vp;
+                    // first column of pair gg at s + 1 = first column of pair gg + 1 at s
+                    const double fa = quad_perm<QP_NEXT>(vf[k]);
+                    const double fb = quad_perm<QP_L0>(vf[k + 1 < SLOTS ? k + 1 : k]);
+                    nf[k] = gg == G - 1 ? vs[k] : (vp < 3 ? fa : fb);
+                    // second column of pair gg at s + 1 = second column of pair gg - 1 at s
+                    const double sa = quad_perm<QP_PREV>(vs[k]);
+                    const double sb = quad_perm<QP_L3>(vs[k > 0 ? k - 1 : 0]);
+                    const double s0 = quad_perm<QP_L0>(vf[0]);
+                    ns[k] = gg == 0 ? vs[0] : (gg == 1 ? s0 : (vp > 0 ? sa : sb));
+                }
+#pragma unroll
+                for (int k = 0; k < SLOTS; ++k) {
+                    const int gg = 4 * k + vp;
+                    vf[k] = nf[k];
+                    vs[k] = ns[k];
+                    // both indices advance by one (mod L); pair 0 keeps the fixed column L
+                    cf[k] = cf[k] + 1 == L ? 0 : cf[k] + 1;
+                    cs[k] = gg == 0 ? L : (cs[k] + 1 == L ? 0 : cs[k] + 1);
+                }
+            }
+            sweeps = sw + 1;
+            if (!__syncthreads_or(rotated)) {
+                converged = true;
+                break;
+            }
+        }
+    }
+    // the schedule has completed whole sweeps: cf / cs are the columns of step 0 again
+
+    for (int c = t / 4; c < NMAX; c += NT / 4) {
+        const int part = t & 3;
+        double sq = 0.0;
+        for (int r = part; r < N; r += 4) sq = fma(sA[r + c * LDA], sA[r + c * LDA], sq);
+        sq += __shfl_xor(sq, 1, 64);
+        sq += __shfl_xor(sq, 2, 64);
+        if (part == 0) snorm[c] = sqrt(sq);
+    }
+    __syncthreads();
+    for (int c = t; c < N; c += NT) {
+        const double sc = snorm[c];
+        int rank = 0;
+        for (int q = 0; q < N; ++q) {
+            const double sq = snorm[q];
+            rank += (sq > sc || (sq == sc && q < c)) ? 1 : 0;
+        }
+        srank[c] = rank;
+    }
+    __syncthreads();
+    double *S = static_cast<double *>(D.S);
+    if (bad) {
+        for (int c = t; c < N; c += NT) S[c] = __builtin_nan("");
+    } else {
+        for (int c = t; c < N; c += NT) S[srank[c]] = snorm[c];
+        // sorted V (the rotations) to D.U from the registers
+        double *Rf = static_cast<double *>(D.U);
+        const int ldr = D.ldu;
+        if (vr < N) {
+#pragma unroll
+            for (int k = 0; k < SLOTS; ++k) {
+                const int gg = 4 * k + vp;
+                if (gg < G) {
+                    if (cf[k] < N) Rf[vr + (size_t)srank[cf[k]] * ldr] = vf[k];
+                    if (cs[k] < N) Rf[vr + (size_t)srank[cs[k]] * ldr] = vs[k];
+                }
+            }
+        }
+        // normalised columns of the working matrix to D.V
+        double *Vg = static_cast<double *>(D.V);
+        const int ldv = D.ldv;
+        for (int c = t / 4; c < N; c += NT / 4) {
+            const int part = t & 3;
+            const double sc = snorm[c];
+            const double inv = sc > 0.0 ? 1.0 / sc : 0.0;
+            for (int r = part; r < N; r += 4) Vg[r + (size_t)srank[c] * ldv] = sA[r + c * LDA] * inv;
+        }
+    }
+    if (t == 0) {
+        if (info_out) info_out[inst] = bad ? INFO_NONFINITE : (converged ? INFO_OK : INFO_SWEEPS);
+        if (sweeps_out) sweeps_out[inst] = bad ? 0 : sweeps;
+    }
+}
+
 template <int NMAX, bool VLDS>
 static hipError_t lds_wide_one(const SvdDesc *d, const int *list, int count, double tol, int max_sweeps, int *sweeps,
                                int *info, hipStream_t st) {
@@ -356,7 +587,15 @@ hipError_t launch_jacobi_lds_wide(int nmax, const SvdDesc *d, const int *list, i
                                   int *sweeps, int *info, hipStream_t st) {
     if (count <= 0) return hipSuccess;
     if (nmax == 96) return lds_wide_one<96, true>(d, list, count, tol, max_sweeps, sweeps, info, st);
-    if (nmax == 128) return lds_wide_one<128, false>(d, list, count, tol, max_sweeps, sweeps, info, st);
+    if (nmax == 128) {
+        const size_t bytes = sizeof(double) * (size_t)(128 + 1) * 128;
+        hipError_t e = hipFuncSetAttribute((const void *)jacobi_lds_vreg_kernel,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(jacobi_lds_vreg_kernel, dim3(count), dim3(512), bytes, st, d, list, tol, max_sweeps,
+                           sweeps, info);
+        return hipGetLastError();
+    }
     return hipErrorInvalidValue;
 }
 

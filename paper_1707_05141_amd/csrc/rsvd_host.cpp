@@ -852,6 +852,77 @@ static int rsvd_range(Ctx *c, int inst_base, int batch, const int *m, const int 
         }
         if (!wide.empty() && (rc = panel_qr(wide))) return rc;
 
+        // SVD path of each R_B class above 64 columns (sizes rounded up to 32): block Jacobi on the
+        // columns of R_B with the width chosen by the autotuner on the first call that meets the
+        // class (kind 1 of the tuning cache); up to 128 columns the single-kernel LDS Jacobi on the
+        // rows of R_B is a further candidate (width 0). The block runs use the auxiliary workspace.
+        std::vector<int> bm(F, 0), bn(F, 0), blda(F, 1), bldu(F, 1);
+        std::vector<const void *> bA(F, nullptr);
+        std::vector<void *> bS(F, nullptr), bU(F, nullptr), bV(F, nullptr);
+        std::map<int, int> class_w;
+        {
+            std::map<int, std::vector<int>> cls;
+            for (int i = 0; i < F; ++i) {
+                const Inst &q = I[finished[i]];
+                if (q.ell <= PANEL) continue;
+                cls[cdiv(q.ell, 32) * 32].push_back(i);
+                bm[i] = q.ell;
+                bn[i] = q.ell;
+                blda[i] = q.cap;
+                bldu[i] = q.cap;
+                bA[i] = dptr(q.oRB);
+                bS[i] = dptr(q.oSig);
+                bU[i] = dptr(q.oVR);
+                bV[i] = dptr(q.oUR);
+            }
+            if (!cls.empty()) {
+                AuxWorkspace aux(c);
+                for (auto &kv : cls) {
+                    const int csz = kv.first;
+                    // the single-kernel candidate: LDS Jacobi on the rows of R_B of the sample
+                    std::function<int(const std::vector<int> &)> lds_run = [&](const std::vector<int> &smp) -> int {
+                        const size_t nd = smp.size();
+                        const size_t by = sizeof(SvdDesc) * nd + sizeof(int) * nd + 64;
+                        int r2 = c->ensure_host(by);
+                        if (r2) return r2;
+                        if ((r2 = c->ensure_device(by))) return r2;
+                        SvdDesc *hd = static_cast<SvdDesc *>(c->hws);
+                        int *hli = reinterpret_cast<int *>(hd + nd);
+                        for (size_t k = 0; k < nd; ++k) {
+                            const Inst &q = I[finished[smp[k]]];
+                            SvdDesc &d = hd[k];
+                            std::memset(&d, 0, sizeof d);
+                            d.A = dptr(q.oRB); d.m = q.ell; d.n = q.ell; d.lda = q.cap; d.trans = 1;
+                            d.M = q.ell; d.N = q.ell;
+                            d.S = dptr(q.oSig); d.U = dptr(q.oVR); d.ldu = q.cap; d.V = dptr(q.oUR); d.ldv = q.cap;
+                            hli[k] = (int)k;
+                        }
+                        if ((r2 = c->upload(by))) return r2;
+                        const SvdDesc *dd = static_cast<const SvdDesc *>(c->dws);
+                        hipError_t e2 = launch_jacobi_lds_wide(csz <= 96 ? 96 : 128, dd,
+                                                               reinterpret_cast<const int *>(dd + nd), (int)nd, 1e-15,
+                                                               60, nullptr, nullptr, c->stream);
+                        return e2 == hipSuccess ? BSVD_OK : c->hip_fail(e2, "wide jacobi launch (tuning)");
+                    };
+                    int w = BLOCK_W;
+                    // BSVD_RB_WIDTH in the environment (0, 8, 16 or 32) fixes the choice, e.g. to test
+                    // each path on its own; 0 (single kernel) applies up to 128 columns only
+                    if (const char *ov = std::getenv("BSVD_RB_WIDTH")) {
+                        const int fw = std::atoi(ov);
+                        if (fw == 0 || fw == 8 || fw == 16 || fw == 32) {
+                            class_w[csz] = (fw == 0 && csz > WIDE_LDS) ? BLOCK_W : fw;
+                            continue;
+                        }
+                    }
+                    rc = tune_block_width(c, BSVD_F64, csz, csz, kv.second, bm.data(), bn.data(), bA.data(),
+                                          blda.data(), bS.data(), bU.data(), bldu.data(), bV.data(), bldu.data(),
+                                          1e-15, 60, &w, 1, csz <= WIDE_LDS ? &lds_run : nullptr);
+                    if (rc) return rc;
+                    class_w[csz] = w;
+                }
+            }
+        }
+
         Packer p;
         if ((rc = new_packer(p))) return rc;
         std::vector<QrDesc> qv;
@@ -869,7 +940,7 @@ static int rsvd_range(Ctx *c, int inst_base, int batch, const int *m, const int 
             hl[i] = b;
             SvdDesc &d = hsd[i];
             std::memset(&d, 0, sizeof d);
-            if (q.ell > WIDE_LDS) {
+            if (q.ell > PANEL && class_w[cdiv(q.ell, 32) * 32] > 0) {
                 blk_pos.push_back(i);
                 continue;
             }
@@ -945,7 +1016,7 @@ static int rsvd_range(Ctx *c, int inst_base, int batch, const int *m, const int 
                 const double l = I[finished[i]].ell;
                 by += 8.0 * (3.0 * l * l + l);
             }
-            pi = c->prof ? c->prof_begin(BSVD_STAGE_JACOBI, h ? "jacobi_lds_wide_kernel<128, false>"
+            pi = c->prof ? c->prof_begin(BSVD_STAGE_JACOBI, h ? "jacobi_lds_vreg_kernel"
                                                                : "jacobi_lds_wide_kernel<96, true>")
                          : -1;
             e = launch_jacobi_lds_wide(h ? 128 : 96, dsd, h ? dwl_hi : dwl_lo, (int)v.size(), 1e-15, 60, djsweeps,
@@ -957,43 +1028,15 @@ static int rsvd_range(Ctx *c, int inst_base, int batch, const int *m, const int 
         if (!blk_pos.empty()) {
             // block Jacobi on the columns of R_B (in the auxiliary workspace): left vectors -> V_R,
             // right vectors -> U_R; info and sweeps by position
-            const int nb = (int)blk_pos.size();
-            std::vector<int> bm(F, 0), bn(F, 0), blda(F, 1), bldu(F, 1);
-            std::vector<const void *> bA(F, nullptr);
-            std::vector<void *> bS(F, nullptr), bU(F, nullptr), bV(F, nullptr);
-            for (int i : blk_pos) {
-                const Inst &q = I[finished[i]];
-                bm[i] = q.ell;
-                bn[i] = q.ell;
-                blda[i] = q.cap;
-                bldu[i] = q.cap;
-                bA[i] = dptr(q.oRB);
-                bS[i] = dptr(q.oSig);
-                bU[i] = dptr(q.oVR);
-                bV[i] = dptr(q.oUR);
-            }
             AuxWorkspace aux(c);
-            // block width per class of padded size (multiples of 32), chosen by the autotuner on the
-            // first call that meets the class (kind 1 of the tuning cache) and reused afterwards
-            std::map<int, std::vector<int>> cls;
-            for (int i : blk_pos) cls[cdiv(bm[i], 32) * 32].push_back(i);
             std::map<int, std::vector<int>> byw;
-            for (auto &kv : cls) {
-                int w = BLOCK_W;
-                rc = tune_block_width(c, BSVD_F64, kv.first, kv.first, kv.second, bm.data(), bn.data(), bA.data(),
-                                      blda.data(), bS.data(), bU.data(), bldu.data(), bV.data(), bldu.data(), 1e-15, 60,
-                                      &w, 1);
-                if (rc) return rc;
-                auto &v = byw[w];
-                v.insert(v.end(), kv.second.begin(), kv.second.end());
-            }
+            for (int i : blk_pos) byw[class_w[cdiv(bm[i], 32) * 32]].push_back(i);
             for (auto &kv : byw) {
                 rc = block_jacobi_run(c, BSVD_F64, kv.first, kv.second, bm.data(), bn.data(), bA.data(), blda.data(),
                                       bS.data(), bU.data(), bldu.data(), bV.data(), bldu.data(), 1e-15, 60, djsweeps,
                                       djinfo);
                 if (rc) return rc;
             }
-            (void)nb;
         }
         pi = c->prof_begin(BSVD_STAGE_SMALL, "finalize_kernel");
         e = launch_finalize(dstate, dl, F, rank, err_est, info, djinfo, drankc, samples, c->stream);

@@ -268,6 +268,32 @@ def test_rsvd_fixed_wide_initial_block_vs_oracle():
         assert abs(rel ** 2 - float(res["err_est"][b]) ** 2) <= 100 * 2.2e-16
 
 
+@pytest.mark.parametrize("width", ["0", "8", "16", "32"])
+def test_rsvd_rb_svd_paths_vs_oracle(width, monkeypatch):
+    """Each SVD path of the R_B factors above 64 columns, forced: single-kernel LDS Jacobi (V in LDS
+    up to 96 columns, V in registers for 97..128; width 0) and block Jacobi of width 8 / 16 / 32.
+    Fixed sample counts cover even and odd sizes on both sides of 96 and 128; singular values against
+    the oracle's Algorithm 4, orthonormal factors and the error identity."""
+    monkeypatch.setenv("BSVD_RB_WIDTH", width)
+    mats = _gd_batch()[:4] + _gd_batch()[:4]
+    buf, offs, m, n = P.pack_colmajor(mats)
+    ell = np.array([97, 128, 101, 77, 127, 120, 113, 96])
+    print("case: R_B SVD path width=%s, ell=%s" % (width, list(ell)), flush=True)
+    res = P.rsvd_packed(buf, offs, m, n, eps=EPS, max_rank=256, seed=23, flags=_lib.RSVD_FIXED, ell0=ell)
+    torch.cuda.synchronize()
+    for b, A in enumerate(mats):
+        mm, nn = A.shape
+        o = oracle.rsvd_fixed(A, ell=int(min(ell[b], mm, nn)), seed=23, inst=b, eps=EPS, max_rank=256)
+        S, U, V = _unpack(res, mm, nn, b)
+        assert len(S) == o["rank"] or _ambiguous(A, EPS, o["rank"])
+        k = min(len(S), o["rank"])
+        np.testing.assert_allclose(S[:k], o["S"][:k], rtol=0, atol=1e-12 * o["S"][0])
+        assert np.linalg.norm(U.T @ U - np.eye(len(S))) <= 1e-11, b
+        assert np.linalg.norm(V.T @ V - np.eye(len(S))) <= 1e-11, b
+        rel = np.linalg.norm(A - (U * S) @ V.T) / np.linalg.norm(A)
+        assert abs(rel ** 2 - float(res["err_est"][b]) ** 2) <= 100 * 2.2e-16
+
+
 def test_rsvd_split_into_sub_batches_is_bitwise_identical(monkeypatch):
     """A workspace budget small enough to force several sub-batches gives the same bits: the
     Gaussian draws are indexed by the instance's position in the whole batch."""
