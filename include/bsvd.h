@@ -117,11 +117,15 @@ int bsvd_profile_kernels(bsvd_ctx *ctx, char *buf, int cap);
 
 /* Autotuner cache. Without a BSVD_SVD_BLOCK_W* flag, the first batched_svd call that sends a
  * (dtype, M, N) class (M = max(m, n), N = min(m, n)) to the block path times widths 8, 16 and 32 on up
- * to 512 of its instances and keeps the fastest in the context (kind 0). batched_rsvd does the same
- * for the block Jacobi SVD of its R_B factors wider than 64 columns, per class of sizes padded to a
- * multiple of 32 (kind 1, M = N = the padded size).
+ * to 2048 of its instances (spread over the class, best of two runs each) and keeps the fastest in
+ * the context (kind 0). batched_rsvd does the same for the SVD of its R_B factors wider than 64
+ * columns, per class of sizes padded to a multiple of 32 (kind 1, M = N = the padded size); up to 128
+ * columns the single-kernel LDS Jacobi is a further candidate, reported as value 0. A class met
+ * again with more than four times the instances its choice was timed on is timed again (choices
+ * loaded from a file are kept).
  *   bsvd_tune_get   value chosen for (kind, dtype, M, N) and up to max_cand (candidate, ms) pairs
- *                   (host arrays, nullable); BSVD_EARG if the class was never tuned
+ *                   (host arrays, nullable; unused candidate slots hold -1); BSVD_EARG if the class
+ *                   was never tuned
  *   bsvd_tune_save  write the cache as text lines "kind dtype M N value"
  *   bsvd_tune_load  merge such a file into the context's cache (entries that name an unsupported
  *                   width are skipped) */

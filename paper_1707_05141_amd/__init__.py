@@ -171,7 +171,7 @@ def tune_get(kind, dtype, M, N, device=None):
     rc = _lib.lib().bsvd_tune_get(ctx.h, int(kind), int(dtype), int(M), int(N), ctypes.byref(v), t, cnd, 8)
     if rc != 0:
         return None
-    return v.value, {cnd[i]: t[i] for i in range(8) if cnd[i]}
+    return v.value, {cnd[i]: t[i] for i in range(8) if cnd[i] >= 0}
 
 
 def tune_save(path, device=None):

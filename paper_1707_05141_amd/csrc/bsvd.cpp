@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <climits>
 #include <cstdarg>
 #include <cstdio>
 #include <algorithm>
@@ -125,22 +126,34 @@ void Ctx::prof_end(int idx, double bytes, double flops) {
     r.flops = flops;
 }
 
-// Time the candidate block widths (and the optional single-kernel path, width 0) on up to 512
+// Time the candidate block widths (and the optional single-kernel path, width 0) on up to 2048
 // instances of the class (writing into their own outputs, which the full run then overwrites) and
-// keep the fastest; cached per context. The sample is large enough to fill the GPU with (matrix,
-// block pair) tasks, so the timing reflects the throughput regime of a large batch rather than the
-// latency of a few matrices.
+// keep the fastest; cached per context. The sample spreads over the whole class and is large enough
+// to fill the GPU several times over with (matrix, block pair) tasks for every width, so the timing
+// reflects the throughput regime of a large batch rather than the latency of a few matrices or the
+// tail of a single wave of workgroups; each candidate is timed twice and its faster run counts (the
+// first run of a kernel also pays its code load).
 int tune_block_width(Ctx *c, int dtype, int M, int N, const std::vector<int> &cls, const int *m, const int *n,
                      const void *const *A, const int *lda, void *const *S, void *const *U, const int *ldu,
                      void *const *V, const int *ldv, double tol, int max_sweeps, int *bw, int kind,
                      const std::function<int(const std::vector<int> &)> *alt) {
+    constexpr size_t TUNE_SAMPLE = 2048;
     const auto key = std::make_tuple(kind, dtype, M, N);
     auto it = c->tune.find(key);
     if (it != c->tune.end()) {
-        *bw = it->second;
-        return BSVD_OK;
+        auto tn = c->tune_n.find(key);
+        const size_t timed_on = tn == c->tune_n.end() ? (size_t)INT_MAX : (size_t)tn->second;
+        if (4 * timed_on >= std::min(cls.size(), TUNE_SAMPLE)) {
+            *bw = it->second;
+            return BSVD_OK;
+        }
     }
-    std::vector<int> sample(cls.begin(), cls.begin() + std::min<size_t>(cls.size(), 512));
+    std::vector<int> sample;
+    if (cls.size() <= TUNE_SAMPLE) {
+        sample = cls;
+    } else {
+        for (size_t k = 0; k < TUNE_SAMPLE; ++k) sample.push_back(cls[k * cls.size() / TUNE_SAMPLE]);
+    }
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return c->fail(BSVD_EHIP, "hipEventCreate");
@@ -153,20 +166,24 @@ int tune_block_width(Ctx *c, int dtype, int M, int N, const std::vector<int> &cl
     if (alt) cands.push_back(0);
     for (int w : {8, 16, 32}) cands.push_back(w);
     for (int w : cands) {
-        hipEventRecord(e0, c->stream);
-        int rc = w == 0 ? (*alt)(sample)
-                        : block_jacobi_run(c, dtype, w, sample, m, n, A, lda, S, U, ldu, V, ldv, tol, max_sweeps,
-                                           nullptr, nullptr);
-        if (rc) {
-            c->prof = prof;
-            hipEventDestroy(e0);
-            hipEventDestroy(e1);
-            return rc;
+        float ms = -1.0f;
+        for (int rep = 0; rep < 2; ++rep) {
+            hipEventRecord(e0, c->stream);
+            int rc = w == 0 ? (*alt)(sample)
+                            : block_jacobi_run(c, dtype, w, sample, m, n, A, lda, S, U, ldu, V, ldv, tol, max_sweeps,
+                                               nullptr, nullptr);
+            if (rc) {
+                c->prof = prof;
+                hipEventDestroy(e0);
+                hipEventDestroy(e1);
+                return rc;
+            }
+            hipEventRecord(e1, c->stream);
+            hipEventSynchronize(e1);
+            float t = 0.0f;
+            hipEventElapsedTime(&t, e0, e1);
+            if (ms < 0.0f || t < ms) ms = t;
         }
-        hipEventRecord(e1, c->stream);
-        hipEventSynchronize(e1);
-        float ms = 0.0f;
-        hipEventElapsedTime(&ms, e0, e1);
         times.push_back({w, ms});
         if (best_t < 0.0f || ms < best_t) {
             best_t = ms;
@@ -178,6 +195,7 @@ int tune_block_width(Ctx *c, int dtype, int M, int N, const std::vector<int> &cl
     hipEventDestroy(e1);
     c->tune[key] = best;
     c->tune_times[key] = times;
+    c->tune_n[key] = (int)sample.size();
     *bw = best;
     return BSVD_OK;
 }
@@ -204,7 +222,7 @@ int bsvd_tune_get(bsvd_ctx *ctx, int kind, int dtype, int M, int N, int *value, 
             ++k;
         }
     for (; k < max_cand; ++k) {
-        if (candidates) candidates[k] = 0;
+        if (candidates) candidates[k] = -1;
         if (times_ms) times_ms[k] = 0.0f;
     }
     return BSVD_OK;
@@ -234,8 +252,12 @@ int bsvd_tune_load(bsvd_ctx *ctx, const char *path) {
         if (line[0] == '#') continue;
         int k, d, M, N, v;
         if (sscanf(line, "%d %d %d %d %d", &k, &d, &M, &N, &v) == 5) {
-            if (k == 0 && v != 8 && v != 16 && v != 32) continue;  // only widths the kernels support
+            // only widths the kernels support; kind 1 also allows the single-kernel path (0) up to 128
+            const bool width_ok = v == 8 || v == 16 || v == 32;
+            if (k == 0 && !width_ok) continue;
+            if (k == 1 && !(width_ok || (v == 0 && M <= 128 && N <= 128))) continue;
             c->tune[std::make_tuple(k, d, M, N)] = v;
+            c->tune_n[std::make_tuple(k, d, M, N)] = INT_MAX;
             ++n;
         }
     }

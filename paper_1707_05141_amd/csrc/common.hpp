@@ -53,9 +53,9 @@ hipError_t launch_qr(int dtype, int nb, int seg, int kr, const QrDesc *d, const 
 bool jacobi_lds_supported(int dtype, int M, int N, int *mmax, int *nmax);
 hipError_t launch_jacobi_lds(int dtype, int mmax, int nmax, const SvdDesc *d, const int *list, int count, double tol,
                              int max_sweeps, int *sweeps, int *info, hipStream_t st);
-// Square FP64 R factors of 65..128 columns, rotated by rows (trans = 1); nmax 96 (V in LDS) or 128
-// (V in global memory); D.U and D.V required (D.V may serve as the V scratch and then receives the
-// normalised columns).
+// Square FP64 R factors of 65..128 columns, rotated by rows (trans = 1): nmax 96 (working matrix and
+// V in LDS) or 128 (working matrix in LDS, V in registers). Sorted rotations (V of the rows) go to
+// D.U, normalised columns of the working matrix to D.V; both required.
 hipError_t launch_jacobi_lds_wide(int nmax, const SvdDesc *d, const int *list, int count, double tol,
                                   int max_sweeps, int *sweeps, int *info, hipStream_t st);
 hipError_t launch_gemm_small(int dtype, const GemmDesc *d, const int *list, int count, hipStream_t st);

@@ -53,6 +53,10 @@ struct Ctx {
     // candidate (kind 0 = block-Jacobi width).
     std::map<std::tuple<int, int, int, int>, int> tune;
     std::map<std::tuple<int, int, int, int>, std::vector<std::pair<int, float>>> tune_times;
+    // instances the cached choice was timed on (INT_MAX for entries loaded from a file): a class met
+    // later with far more instances is timed again, since small samples favour the low-latency
+    // choices over the high-throughput ones
+    std::map<std::tuple<int, int, int, int>, int> tune_n;
 
     // Profiling: HIP events recorded on `stream` around launches (off by default). Each record
     // names its stage and, when it brackets exactly one kernel launch, that kernel.

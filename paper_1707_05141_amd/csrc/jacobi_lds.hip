@@ -16,10 +16,32 @@
 
 namespace bsvd {
 
+// Lane moves of a double inside rows of 16 lanes (DPP): the control selects the source lane.
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double x) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+constexpr int DPP_XOR1 = 1 | (0 << 2) | (3 << 4) | (2 << 6);  // quad_perm [1, 0, 3, 2]
+constexpr int DPP_XOR2 = 2 | (3 << 2) | (0 << 4) | (1 << 6);  // quad_perm [2, 3, 0, 1]
+constexpr int DPP_ROW_MIRROR = 0x140;                         // lane i <- 15 - i (in a row of 16)
+constexpr int DPP_ROW_HALF_MIRROR = 0x141;                    // lane i <- 7 - i (in a half row)
+
+// Sum over aligned groups of LPP lanes, the same bits in every lane of the group. Up to 16 lanes
+// the partial sums move by DPP (no trip through the LDS crossbar): mirror folds first (lane i adds
+// lane 15 - i, then 7 - i), then the quad exchanges; every lane adds the same two values at each
+// level, in the same order as its partner. Wider groups finish with shuffles.
 template <int LPP>
 __device__ __forceinline__ double grp_sum(double v) {
-#pragma unroll
-    for (int o = LPP / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    static_assert(LPP >= 1 && LPP <= 64 && (LPP & (LPP - 1)) == 0, "power-of-two group");
+    if constexpr (LPP >= 16) v += dpp_d<DPP_ROW_MIRROR>(v);
+    if constexpr (LPP >= 8) v += dpp_d<DPP_ROW_HALF_MIRROR>(v);
+    if constexpr (LPP >= 2) v += dpp_d<DPP_XOR1>(v);
+    if constexpr (LPP >= 4) v += dpp_d<DPP_XOR2>(v);
+    if constexpr (LPP >= 32) v += __shfl_xor(v, 16, 64);
+    if constexpr (LPP >= 64) v += __shfl_xor(v, 32, 64);
     return v;
 }
 
@@ -67,36 +89,44 @@ __global__ __launch_bounds__(256) void jacobi_lds_kernel(const SvdDesc *__restri
 
     const int g = t / LPP;  // pair slot
     const int l = t - g * LPP;
+    // circle schedule: pair g holds columns (s + g, s - g) mod L, pair 0 holds (s, L); both advance
+    // by one per step and return to their step-0 values after a sweep. Pair slots past NP / 2 are
+    // idle but keep valid column indices. Rows past M and columns past N are zero in the LDS, so the
+    // lanes read and rotate whole rows without bounds tests when MMAX is a multiple of LPP.
+    const int L = NP - 1;
+    int wp = g == 0 ? 0 : g % L;
+    int wq = g == 0 ? L : (L - g % L) % L;
+    constexpr bool FULL = MMAX % LPP == 0;
+    constexpr bool VFULL = NMAX % LPP == 0;
     int sweeps = 0;
     bool converged = false;
     if (!bad) {
         for (int sw = 0; sw < max_sweeps; ++sw) {
             int rotated = 0;
-            for (int s = 0; s < NP - 1; ++s) {
-                int p, q;
-                if (g == 0) {
-                    p = s;
-                    q = NP - 1;
-                } else {
-                    const int L = NP - 1;
-                    p = (s + g) % L;
-                    q = ((s - g) % L + L) % L;
-                }
-                const int i = p < q ? p : q;
-                const int j = p < q ? q : p;
+            for (int s = 0; s < L; ++s) {
+                const int i = wp < wq ? wp : wq;
+                const int j = wp < wq ? wq : wp;
+                wp = wp + 1 == L ? 0 : wp + 1;
+                wq = g == 0 ? L : (wq + 1 == L ? 0 : wq + 1);
                 const bool live = g < NP / 2;
                 double alpha = 0.0, beta = 0.0, gam = 0.0;
                 T ai[RPL], aj[RPL];
-                if (live) {
 #pragma unroll
-                    for (int k = 0; k < RPL; ++k) {
-                        const int r = l + LPP * k;
-                        ai[k] = (r < MMAX) ? sA[r + i * LDA] : T(0);
-                        aj[k] = (r < MMAX) ? sA[r + j * LDA] : T(0);
-                        alpha = fma((double)ai[k], (double)ai[k], alpha);
-                        beta = fma((double)aj[k], (double)aj[k], beta);
-                        gam = fma((double)ai[k], (double)aj[k], gam);
-                    }
+                for (int k = 0; k < RPL; ++k) {
+                    const int r = l + LPP * k;
+                    ai[k] = (FULL || r < MMAX) ? sA[r + i * LDA] : T(0);
+                    aj[k] = (FULL || r < MMAX) ? sA[r + j * LDA] : T(0);
+                    alpha = fma((double)ai[k], (double)ai[k], alpha);
+                    beta = fma((double)aj[k], (double)aj[k], beta);
+                    gam = fma((double)ai[k], (double)aj[k], gam);
+                }
+                // V rows fetched before the reductions so that their latency overlaps them
+                T vi[VPL], vj[VPL];
+#pragma unroll
+                for (int k = 0; k < VPL; ++k) {
+                    const int r = l + LPP * k;
+                    vi[k] = (VFULL || r < NMAX) ? sV[r + i * LDV] : T(0);
+                    vj[k] = (VFULL || r < NMAX) ? sV[r + j * LDV] : T(0);
                 }
                 alpha = grp_sum<LPP>(alpha);
                 beta = grp_sum<LPP>(beta);
@@ -109,7 +139,7 @@ __global__ __launch_bounds__(256) void jacobi_lds_kernel(const SvdDesc *__restri
 #pragma unroll
                     for (int k = 0; k < RPL; ++k) {
                         const int r = l + LPP * k;
-                        if (r < MMAX) {
+                        if (FULL || r < MMAX) {
                             sA[r + i * LDA] = cc * ai[k] - ss * aj[k];
                             sA[r + j * LDA] = ss * ai[k] + cc * aj[k];
                         }
@@ -117,10 +147,9 @@ __global__ __launch_bounds__(256) void jacobi_lds_kernel(const SvdDesc *__restri
 #pragma unroll
                     for (int k = 0; k < VPL; ++k) {
                         const int r = l + LPP * k;
-                        if (r < NMAX) {
-                            const T vi = sV[r + i * LDV], vj = sV[r + j * LDV];
-                            sV[r + i * LDV] = cc * vi - ss * vj;
-                            sV[r + j * LDV] = ss * vi + cc * vj;
+                        if (VFULL || r < NMAX) {
+                            sV[r + i * LDV] = cc * vi[k] - ss * vj[k];
+                            sV[r + j * LDV] = ss * vi[k] + cc * vj[k];
                         }
                     }
                     rotated = 1;
@@ -178,15 +207,12 @@ __global__ __launch_bounds__(256) void jacobi_lds_kernel(const SvdDesc *__restri
     }
 }
 
-// Square FP64 working matrices of 65..128 columns (the R_B factors of wide randomized-SVD bases,
-// rotated by rows: trans = 1). Up to 96 columns the working matrix and V both fit the LDS
-// (2 x 97 x 96 doubles); beyond, the working matrix alone fills it (128 x 129 doubles) and V lives in
-// global memory -- in the caller's left-factor output D.V, used as scratch (L2-resident, 128 KB per
-// matrix) and overwritten with the normalised columns at the end, after the sorted V has been copied
-// to D.U. The global V rows of a step are loaded at the start of the step, so their latency overlaps
-// the Gram sums and reductions. 512 threads: LPP = 8 lanes per pair, each lane holding rows
-// l, l + 8, ... of both columns. Otherwise as jacobi_lds_kernel.
-template <int NMAX, bool VLDS>
+// Square FP64 working matrices of 65..96 columns (the R_B factors of wide randomized-SVD bases,
+// rotated by rows: trans = 1): the working matrix and V both fit the LDS (2 x 97 x 96 doubles).
+// 512 threads: LPP = 8 lanes per pair, each lane holding rows l, l + 8, ... of both columns; the
+// padding rows and columns are zero, so the lanes read and rotate whole rows without bounds tests.
+// Schedule, rotation rule and test as jacobi_lds_kernel.
+template <int NMAX>
 __global__ __launch_bounds__(512) void jacobi_lds_wide_kernel(const SvdDesc *__restrict__ descs,
                                                               const int *__restrict__ list, double tol,
                                                               int max_sweeps, int *__restrict__ sweeps_out,
@@ -195,9 +221,10 @@ __global__ __launch_bounds__(512) void jacobi_lds_wide_kernel(const SvdDesc *__r
     constexpr int LPP = 8;
     constexpr int RPL = NMAX / LPP;
     constexpr int LDA = NMAX + 1;
+    static_assert(NMAX % LPP == 0 && NMAX / 2 * LPP <= NT, "pair slots");
     extern __shared__ unsigned char smem_raw[];
     double *sA = reinterpret_cast<double *>(smem_raw);
-    double *sV = sA + (size_t)LDA * NMAX;  // used when VLDS
+    double *sV = sA + (size_t)LDA * NMAX;
     __shared__ double snorm[NMAX];
 
     const int inst = list[blockIdx.x];
@@ -205,11 +232,8 @@ __global__ __launch_bounds__(512) void jacobi_lds_wide_kernel(const SvdDesc *__r
     const int t = threadIdx.x;
     const int N = D.N;  // square: M == N <= NMAX
     const int NP = (N + 1) & ~1;
+    const int L = NP - 1;
     const double *Ap = static_cast<const double *>(D.A);
-    double *Vg = static_cast<double *>(D.V);  // global V accumulator (scratch) when !VLDS; ld D.ldv
-    const int ldv = D.ldv;
-    double *Vb = VLDS ? sV : Vg;
-    const int ldV = VLDS ? LDA : ldv;
 
     int nonfinite = 0;
     for (int idx = t; idx < LDA * NMAX; idx += NT) {
@@ -218,52 +242,41 @@ __global__ __launch_bounds__(512) void jacobi_lds_wide_kernel(const SvdDesc *__r
         if (c < N && r < N) x = Ap[c + (size_t)r * D.lda];  // rows of the stored matrix
         if (!__builtin_isfinite(x)) nonfinite = 1;
         sA[idx] = x;
-    }
-    for (int idx = t; idx < N * N; idx += NT) {
-        const int c = idx / N, r = idx - c * N;
-        Vb[r + (size_t)c * ldV] = (r == c) ? 1.0 : 0.0;
+        sV[idx] = (r == c && c < N) ? 1.0 : 0.0;
     }
     const int bad = __syncthreads_or(nonfinite);
 
     const int g = t / LPP;
     const int l = t - g * LPP;
+    int wp = g == 0 ? 0 : g % L;
+    int wq = g == 0 ? L : (L - g % L) % L;
     int sweeps = 0;
     bool converged = false;
     if (!bad) {
         for (int sw = 0; sw < max_sweeps; ++sw) {
             int rotated = 0;
-            for (int s = 0; s < NP - 1; ++s) {
-                int p, q;
-                if (g == 0) {
-                    p = s;
-                    q = NP - 1;
-                } else {
-                    const int L = NP - 1;
-                    p = (s + g) % L;
-                    q = ((s - g) % L + L) % L;
-                }
-                const int i = p < q ? p : q;
-                const int j = p < q ? q : p;
+            for (int s = 0; s < L; ++s) {
+                const int i = wp < wq ? wp : wq;
+                const int j = wp < wq ? wq : wp;
+                wp = wp + 1 == L ? 0 : wp + 1;
+                wq = g == 0 ? L : (wq + 1 == L ? 0 : wq + 1);
                 const bool live = g < NP / 2;
-                // V rows first (global: in flight while the Gram entries are formed)
-                double vi[RPL], vj[RPL];
-#pragma unroll
-                for (int k = 0; k < RPL; ++k) {
-                    const int r = l + LPP * k;
-                    const bool ok = live && r < N && j < N;
-                    vi[k] = ok ? Vb[r + (size_t)i * ldV] : 0.0;
-                    vj[k] = ok ? Vb[r + (size_t)j * ldV] : 0.0;
-                }
                 double alpha = 0.0, beta = 0.0, gam = 0.0;
-                double ai[RPL], aj[RPL];
+                double ai[RPL], aj[RPL], vi[RPL], vj[RPL];
 #pragma unroll
                 for (int k = 0; k < RPL; ++k) {
                     const int r = l + LPP * k;
-                    ai[k] = (live && r < N) ? sA[r + i * LDA] : 0.0;
-                    aj[k] = (live && r < N) ? sA[r + j * LDA] : 0.0;
+                    ai[k] = sA[r + i * LDA];
+                    aj[k] = sA[r + j * LDA];
                     alpha = fma(ai[k], ai[k], alpha);
                     beta = fma(aj[k], aj[k], beta);
                     gam = fma(ai[k], aj[k], gam);
+                }
+#pragma unroll
+                for (int k = 0; k < RPL; ++k) {
+                    const int r = l + LPP * k;
+                    vi[k] = sV[r + i * LDA];
+                    vj[k] = sV[r + j * LDA];
                 }
                 alpha = grp_sum<LPP>(alpha);
                 beta = grp_sum<LPP>(beta);
@@ -275,12 +288,10 @@ __global__ __launch_bounds__(512) void jacobi_lds_wide_kernel(const SvdDesc *__r
 #pragma unroll
                     for (int k = 0; k < RPL; ++k) {
                         const int r = l + LPP * k;
-                        if (r < N) {
-                            sA[r + i * LDA] = c * ai[k] - sn * aj[k];
-                            sA[r + j * LDA] = sn * ai[k] + c * aj[k];
-                            Vb[r + (size_t)i * ldV] = c * vi[k] - sn * vj[k];
-                            Vb[r + (size_t)j * ldV] = sn * vi[k] + c * vj[k];
-                        }
+                        sA[r + i * LDA] = c * ai[k] - sn * aj[k];
+                        sA[r + j * LDA] = sn * ai[k] + c * aj[k];
+                        sV[r + i * LDA] = c * vi[k] - sn * vj[k];
+                        sV[r + j * LDA] = sn * vi[k] + c * vj[k];
                     }
                     rotated = 1;
                 }
@@ -296,21 +307,23 @@ __global__ __launch_bounds__(512) void jacobi_lds_wide_kernel(const SvdDesc *__r
 
     for (int c = t / 4; c < NMAX; c += NT / 4) {
         const int part = t & 3;
-        double s = 0.0;
-        for (int r = part; r < N; r += 4) s = fma(sA[r + c * LDA], sA[r + c * LDA], s);
-        s += __shfl_xor(s, 1, 64);
-        s += __shfl_xor(s, 2, 64);
-        if (part == 0) snorm[c] = sqrt(s);
+        double sq = 0.0;
+        for (int r = part; r < N; r += 4) sq = fma(sA[r + c * LDA], sA[r + c * LDA], sq);
+        sq += __shfl_xor(sq, 1, 64);
+        sq += __shfl_xor(sq, 2, 64);
+        if (part == 0) snorm[c] = sqrt(sq);
     }
     __syncthreads();
     double *S = static_cast<double *>(D.S);
     if (bad) {
         for (int c = t; c < N; c += NT) S[c] = __builtin_nan("");
     } else {
+        // sorted V (the rotations) to D.U, the normalised columns of the working matrix to D.V;
+        // each group of 4 threads handles one column: rank by descending norm (stable)
         double *Rf = static_cast<double *>(D.U);
         const int ldr = D.ldu;
-        // sorted V (the rotations) to D.U first, then the normalised columns to D.V (which held V
-        // when it lives in global memory)
+        double *Lf = static_cast<double *>(D.V);
+        const int ldl = D.ldv;
         for (int c = t / 4; c < N; c += NT / 4) {
             const int part = t & 3;
             const double sc = snorm[c];
@@ -320,19 +333,11 @@ __global__ __launch_bounds__(512) void jacobi_lds_wide_kernel(const SvdDesc *__r
                 rank += (sq > sc || (sq == sc && q < c)) ? 1 : 0;
             }
             if (part == 0) S[rank] = sc;
-            for (int r = part; r < N; r += 4) Rf[r + (size_t)rank * ldr] = Vb[r + (size_t)c * ldV];
-        }
-        __syncthreads();
-        for (int c = t / 4; c < N; c += NT / 4) {
-            const int part = t & 3;
-            const double sc = snorm[c];
-            int rank = 0;
-            for (int q = 0; q < N; ++q) {
-                const double sq = snorm[q];
-                rank += (sq > sc || (sq == sc && q < c)) ? 1 : 0;
-            }
             const double inv = sc > 0.0 ? 1.0 / sc : 0.0;
-            for (int r = part; r < N; r += 4) Vg[r + (size_t)rank * ldv] = sA[r + c * LDA] * inv;
+            for (int r = part; r < N; r += 4) {
+                Rf[r + (size_t)rank * ldr] = sV[r + c * LDA];
+                Lf[r + (size_t)rank * ldl] = sA[r + c * LDA] * inv;
+            }
         }
     }
     if (t == 0) {
@@ -342,23 +347,19 @@ __global__ __launch_bounds__(512) void jacobi_lds_wide_kernel(const SvdDesc *__r
 }
 
 // Lane-quad exchange of a double: lane 4q + a receives the value of lane 4q + perm[a], perm given
-// as a DPP quad_perm control (two 32-bit DPP moves).
+// as a DPP quad_perm control.
 template <int CTRL>
 __device__ __forceinline__ double quad_perm(double x) {
-    const unsigned long long b = __builtin_bit_cast(unsigned long long, x);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
-    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+    return dpp_d<CTRL>(x);
 }
 constexpr int QP_NEXT = 1 | (2 << 2) | (3 << 4) | (0 << 6);  // from lane a + 1 (mod 4)
 constexpr int QP_PREV = 3 | (0 << 2) | (1 << 4) | (2 << 6);  // from lane a - 1 (mod 4)
-constexpr int QP_L0 = 0;                                     // from lane 0 of the quad
-constexpr int QP_L3 = 3 | (3 << 2) | (3 << 4) | (3 << 6);    // from lane 3 of the quad
 
 // Square FP64 working matrices of 97..128 columns with the accumulated rotations V in registers.
 // The working matrix fills the LDS (128 x 129 doubles); V is distributed by rows: thread t holds row
-// r = t / 4 of V for the column pairs g = 4 k + (t % 4), k = 0..15, i.e. the two columns that pair g
-// rotates in the current round-robin step. Each step has two phases separated by one barrier:
+// r = t / 4 of V for the column pairs g = 16 (t % 4) + k, k = 0..15 (register slot k), i.e. the two
+// columns that pair g rotates in the current round-robin step. Each step has two phases separated by
+// one barrier:
 //   W phase: pair g (8 lanes, as in the other LDS kernels) forms its Gram entries from the LDS
 //            columns, derives the rotation, stores (c, s) in a double-buffered table and rotates its
 //            two LDS columns;
@@ -366,8 +367,9 @@ constexpr int QP_L3 = 3 | (3 << 2) | (3 << 4) | (3 << 6);    // from lane 3 of t
 //            columns on to the threads that hold them in the next step. In the circle schedule the
 //            column a pair holds first moves to pair g - 1 and the second to pair g + 1 (pair 0 keeps
 //            the fixed last column, the first column of pair 0 becomes the second of pair 1, the
-//            second column of the last pair becomes its first), so every move stays inside a lane
-//            quad (DPP quad permutations) or shifts one register slot at the quad boundary.
+//            second column of the last pair becomes its first), so every move is a shift by one
+//            register slot inside the thread, plus one DPP quad permutation per direction for the
+//            slots that cross to the neighbouring lane of the quad.
 // V never leaves the registers until the sorted output is written, so no step waits on global
 // memory. Rotation rule, ordering, test and outputs are those of jacobi_lds_wide_kernel.
 __global__ __launch_bounds__(512) void jacobi_lds_vreg_kernel(const SvdDesc *__restrict__ descs,
@@ -382,7 +384,7 @@ __global__ __launch_bounds__(512) void jacobi_lds_vreg_kernel(const SvdDesc *__r
     constexpr int SLOTS = NMAX / 2 / 4;  // pairs per V thread
     extern __shared__ unsigned char smem_raw[];
     double *sA = reinterpret_cast<double *>(smem_raw);
-    __shared__ double rot_c[2][NMAX / 2], rot_s[2][NMAX / 2];
+    __shared__ double2 rot_tab[2][NMAX / 2];  // (c, s) of each pair, double-buffered by step parity
     __shared__ double snorm[NMAX];
     __shared__ int srank[NMAX];
 
@@ -414,16 +416,21 @@ __global__ __launch_bounds__(512) void jacobi_lds_vreg_kernel(const SvdDesc *__r
     // columns held by pair gg at step s: first = s + gg, second = s - gg (mod L); pair 0: (s, L)
     auto first_col = [&](int gg, int s) { return gg == 0 ? s : (s + gg) % L; };
     auto second_col = [&](int gg, int s) { return gg == 0 ? L : ((s - gg) % L + L) % L; };
-    double vf[SLOTS], vs[SLOTS];  // V[vr, first / second column of pair 4 k + vp]
+    double vf[SLOTS], vs[SLOTS];  // V[vr, first / second column of pair SLOTS vp + k]
     int cf[SLOTS], cs[SLOTS];     // those column indices at the current step
+    const int k_last = (G - 1) % SLOTS, p_last = (G - 1) / SLOTS;  // slot and lane of the last pair
 #pragma unroll
     for (int k = 0; k < SLOTS; ++k) {
-        const int gg = 4 * k + vp;
+        const int gg = SLOTS * vp + k;
         cf[k] = gg < G ? first_col(gg, 0) : 0;
         cs[k] = gg < G ? second_col(gg, 0) : 0;
         vf[k] = (gg < G && vr < N && cf[k] == vr) ? 1.0 : 0.0;
         vs[k] = (gg < G && vr < N && cs[k] == vr) ? 1.0 : 0.0;
     }
+    // columns of pair g at step 0 (pairs past the last live one index valid columns too: g, L - g)
+    int wp = first_col(g, 0), wq = second_col(g, 0);
+    if (t < NMAX) rot_tab[t / (NMAX / 2)][t % (NMAX / 2)] = make_double2(1.0, 0.0);
+    __syncthreads();
     int sweeps = 0;
     bool converged = false;
     if (!bad) {
@@ -432,17 +439,18 @@ __global__ __launch_bounds__(512) void jacobi_lds_vreg_kernel(const SvdDesc *__r
             for (int s = 0; s < L; ++s) {
                 const int buf = s & 1;
                 {
+                    // rows past N and the padding column are zero in the LDS, so every lane reads
+                    // and writes its 16 rows unconditionally (rotating zeros leaves zeros)
                     const bool live = g < G;
-                    const int p = live ? first_col(g, s) : 0, q = live ? second_col(g, s) : 1;
-                    const int i = p < q ? p : q;
-                    const int j = p < q ? q : p;
+                    const int i = wp < wq ? wp : wq;
+                    const int j = wp < wq ? wq : wp;
                     double alpha = 0.0, beta = 0.0, gam = 0.0;
                     double ai[RPL], aj[RPL];
 #pragma unroll
                     for (int k = 0; k < RPL; ++k) {
                         const int r = l + LPP * k;
-                        ai[k] = (live && r < N) ? sA[r + i * LDA] : 0.0;
-                        aj[k] = (live && r < N) ? sA[r + j * LDA] : 0.0;
+                        ai[k] = sA[r + i * LDA];
+                        aj[k] = sA[r + j * LDA];
                         alpha = fma(ai[k], ai[k], alpha);
                         beta = fma(aj[k], aj[k], beta);
                         gam = fma(ai[k], aj[k], gam);
@@ -457,54 +465,51 @@ __global__ __launch_bounds__(512) void jacobi_lds_vreg_kernel(const SvdDesc *__r
 #pragma unroll
                         for (int k = 0; k < RPL; ++k) {
                             const int r = l + LPP * k;
-                            if (r < N) {
-                                sA[r + i * LDA] = c * ai[k] - sn * aj[k];
-                                sA[r + j * LDA] = sn * ai[k] + c * aj[k];
-                            }
+                            sA[r + i * LDA] = c * ai[k] - sn * aj[k];
+                            sA[r + j * LDA] = sn * ai[k] + c * aj[k];
                         }
                         rotated = 1;
                     }
-                    if (live && l == 0) {
-                        rot_c[buf][g] = c;
-                        rot_s[buf][g] = sn;
-                    }
+                    if (live && l == 0) rot_tab[buf][g] = make_double2(c, sn);
+                    wp = wp + 1 == L ? 0 : wp + 1;
+                    wq = g == 0 ? L : (wq + 1 == L ? 0 : wq + 1);
                 }
                 __syncthreads();
                 // V phase: rotate the row, then move the columns to their holders at step s + 1
+                // (the rotation acts on (column i, column j), i < j: when the held first column is
+                // the larger index the same formulas apply with the sine negated; pairs past the
+                // last live one keep the identity entries of the table)
 #pragma unroll
                 for (int k = 0; k < SLOTS; ++k) {
-                    const int gg = 4 * k + vp;
-                    if (gg < G) {
-                        const double c = rot_c[buf][gg], sn = rot_s[buf][gg];
-                        const double a = vf[k], b = vs[k];
-                        if (cf[k] < cs[k]) {
-                            vf[k] = c * a - sn * b;
-                            vs[k] = sn * a + c * b;
-                        } else {
-                            vs[k] = c * b - sn * a;
-                            vf[k] = sn * b + c * a;
-                        }
-                    }
+                    const double2 r = rot_tab[buf][SLOTS * vp + k];
+                    const double sn = cf[k] < cs[k] ? r.y : -r.y;
+                    const double a = vf[k], b = vs[k];
+                    vf[k] = r.x * a - sn * b;
+                    vs[k] = sn * a + r.x * b;
                 }
-                double nf[SLOTS], ns[SLOTS];
+                // first column of pair g at s + 1 = first column of pair g + 1 at s: the next slot of
+                // the same lane, or slot 0 of the next lane of the quad; second column of pair g at
+                // s + 1 = second column of pair g - 1 at s: the previous slot, or the last slot of the
+                // previous lane. Special holders: the last live pair takes its own second column,
+                // pair 1 the first column of pair 0, pair 0 keeps its second (the fixed column).
+                const double f_next = quad_perm<QP_NEXT>(vf[0]);
+                const double s_prev = quad_perm<QP_PREV>(vs[SLOTS - 1]);
+                const double f0 = vf[0], s0 = vs[0];
 #pragma unroll
                 for (int k = 0; k < SLOTS; ++k) {
-                    const int gg = 4 * k + vp;
-                    // first column of pair gg at s + 1 = first column of pair gg + 1 at s
-                    const double fa = quad_perm<QP_NEXT>(vf[k]);
-                    const double fb = quad_perm<QP_L0>(vf[k + 1 < SLOTS ? k + 1 : k]);
-                    nf[k] = gg == G - 1 ? vs[k] : (vp < 3 ? fa : fb);
-                    // second column of pair gg at s + 1 = second column of pair gg - 1 at s
-                    const double sa = quad_perm<QP_PREV>(vs[k]);
-                    const double sb = quad_perm<QP_L3>(vs[k > 0 ? k - 1 : 0]);
-                    const double s0 = quad_perm<QP_L0>(vf[0]);
-                    ns[k] = gg == 0 ? vs[0] : (gg == 1 ? s0 : (vp > 0 ? sa : sb));
+                    const double own_s = vs[k];
+                    vf[k] = (vp == p_last && k == k_last) ? own_s : (k + 1 < SLOTS ? vf[k + 1] : f_next);
                 }
 #pragma unroll
+                for (int k = SLOTS - 1; k >= 0; --k) {
+                    double v = k > 0 ? vs[k - 1] : s_prev;
+                    if (k == 1) v = vp == 0 ? f0 : v;
+                    if (k == 0) v = vp == 0 ? s0 : v;
+                    vs[k] = v;
+                }
+#pragma unroll
                 for (int k = 0; k < SLOTS; ++k) {
-                    const int gg = 4 * k + vp;
-                    vf[k] = nf[k];
-                    vs[k] = ns[k];
+                    const int gg = SLOTS * vp + k;
                     // both indices advance by one (mod L); pair 0 keeps the fixed column L
                     cf[k] = cf[k] + 1 == L ? 0 : cf[k] + 1;
                     cs[k] = gg == 0 ? L : (cs[k] + 1 == L ? 0 : cs[k] + 1);
@@ -549,7 +554,7 @@ __global__ __launch_bounds__(512) void jacobi_lds_vreg_kernel(const SvdDesc *__r
         if (vr < N) {
 #pragma unroll
             for (int k = 0; k < SLOTS; ++k) {
-                const int gg = 4 * k + vp;
+                const int gg = SLOTS * vp + k;
                 if (gg < G) {
                     if (cf[k] < N) Rf[vr + (size_t)srank[cf[k]] * ldr] = vf[k];
                     if (cs[k] < N) Rf[vr + (size_t)srank[cs[k]] * ldr] = vs[k];
@@ -572,11 +577,11 @@ __global__ __launch_bounds__(512) void jacobi_lds_vreg_kernel(const SvdDesc *__r
     }
 }
 
-template <int NMAX, bool VLDS>
+template <int NMAX>
 static hipError_t lds_wide_one(const SvdDesc *d, const int *list, int count, double tol, int max_sweeps, int *sweeps,
                                int *info, hipStream_t st) {
-    const size_t bytes = sizeof(double) * (size_t)(NMAX + 1) * NMAX * (VLDS ? 2 : 1);
-    auto kern = jacobi_lds_wide_kernel<NMAX, VLDS>;
+    const size_t bytes = sizeof(double) * (size_t)(NMAX + 1) * NMAX * 2;
+    auto kern = jacobi_lds_wide_kernel<NMAX>;
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3(count), dim3(512), bytes, st, d, list, tol, max_sweeps, sweeps, info);
@@ -586,7 +591,7 @@ static hipError_t lds_wide_one(const SvdDesc *d, const int *list, int count, dou
 hipError_t launch_jacobi_lds_wide(int nmax, const SvdDesc *d, const int *list, int count, double tol, int max_sweeps,
                                   int *sweeps, int *info, hipStream_t st) {
     if (count <= 0) return hipSuccess;
-    if (nmax == 96) return lds_wide_one<96, true>(d, list, count, tol, max_sweeps, sweeps, info, st);
+    if (nmax == 96) return lds_wide_one<96>(d, list, count, tol, max_sweeps, sweeps, info, st);
     if (nmax == 128) {
         const size_t bytes = sizeof(double) * (size_t)(128 + 1) * 128;
         hipError_t e = hipFuncSetAttribute((const void *)jacobi_lds_vreg_kernel,

@@ -918,7 +918,7 @@ static int rsvd_range(Ctx *c, int inst_base, int batch, const int *m, const int 
                                           blda.data(), bS.data(), bU.data(), bldu.data(), bV.data(), bldu.data(),
                                           1e-15, 60, &w, 1, csz <= WIDE_LDS ? &lds_run : nullptr);
                     if (rc) return rc;
-                    class_w[csz] = w;
+                    class_w[csz] = (w == 0 && csz > WIDE_LDS) ? BLOCK_W : w;  // a loaded cache may say 0
                 }
             }
         }
@@ -1017,7 +1017,7 @@ static int rsvd_range(Ctx *c, int inst_base, int batch, const int *m, const int 
                 by += 8.0 * (3.0 * l * l + l);
             }
             pi = c->prof ? c->prof_begin(BSVD_STAGE_JACOBI, h ? "jacobi_lds_vreg_kernel"
-                                                               : "jacobi_lds_wide_kernel<96, true>")
+                                                               : "jacobi_lds_wide_kernel<96>")
                          : -1;
             e = launch_jacobi_lds_wide(h ? 128 : 96, dsd, h ? dwl_hi : dwl_lo, (int)v.size(), 1e-15, 60, djsweeps,
                                        djinfo, c->stream);

@@ -85,3 +85,15 @@ def test_block_autotuner_picks_and_persists(tmp_path):
     P.tune_save(p)
     assert "0 0 96 64 %d" % tuned[0] in p.read_text()
     P.tune_load(p)
+
+
+def test_tune_cache_load_rejects_unsupported_values(tmp_path):
+    """A loaded cache may name the single-kernel path (value 0) for R_B classes up to 128 columns
+    only; widths other than 8, 16 and 32 and a 0 above 128 columns are skipped."""
+    p = tmp_path / "tune_bad.txt"
+    p.write_text("# kind dtype M N value\n1 0 96 96 0\n1 0 480 480 0\n1 0 448 448 12\n0 0 400 300 0\n")
+    P.tune_load(p)
+    assert P.tune_get(1, 0, 96, 96)[0] == 0
+    assert P.tune_get(1, 0, 480, 480) is None
+    assert P.tune_get(1, 0, 448, 448) is None
+    assert P.tune_get(0, 0, 400, 300) is None
