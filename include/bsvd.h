@@ -145,13 +145,14 @@ const char *bsvd_version(void);
  * round-robin order, n/2 disjoint pairs at a time (Section 5). Matrices with m < n are handled
  * through their transpose. Rectangular inputs (and square ones with BSVD_SVD_QR_FIRST) are first
  * reduced by Householder QR (Section 2.1), W = Q R; the SVD of the min(m,n) x min(m,n) triangle R is
- * then computed by one-sided Jacobi applied to the columns of R^T (the rows of R), which converges
- * in far fewer sweeps than on R itself (the QR preprocessing that Section 6.3 names as a remedy for
- * slow block-Jacobi convergence), and U = Q U_R. Matrices too large for the register and LDS kernels
+ * then computed by one-sided Jacobi applied to the columns of R^T (the rows of R; the QR
+ * preprocessing that Section 6.3 names as a remedy for slow block-Jacobi convergence), and U = Q U_R. Matrices too large for the register and LDS kernels
  * (or all of them with BSVD_SVD_FORCE_BLOCK) use the one-sided block Jacobi of Section 6.1
- * (Algorithm 3, Gram path): pairs of w-column blocks are orthogonalised by the SVD of their
- * 2w x 2w Gram matrix, visited in round-robin order, until every pair's scaled off-diagonal
- * max |G_ab| / sqrt(G_aa G_bb) is <= tol; sweeps then counts block sweeps.
+ * (Algorithm 3, Gram path): pairs of w-column blocks are rotated by the right singular vectors of
+ * their 2w x 2w Gram matrix G (one-sided Jacobi on G, at most two sweeps per visit: an orthogonal
+ * block rotation that removes most of G's off-diagonal mass), visited in round-robin order, until
+ * every pair's scaled off-diagonal max |G_ab| / sqrt(G_aa G_bb) is <= tol; sweeps then counts
+ * block sweeps.
  *
  *   dtype       BSVD_F64 (or BSVD_F32: data and rotations in FP32, angles and norms in FP64)
  *   batch       number of instances (0 is allowed and does nothing)

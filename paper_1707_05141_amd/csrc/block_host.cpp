@@ -21,6 +21,8 @@
 
 namespace bsvd {
 
+constexpr int BJ_INNER_SWEEPS = 2;
+
 int block_jacobi_run(Ctx *c, int dtype, int w, const std::vector<int> &insts, const int *m, const int *n,
                      const void *const *A, const int *lda, void *const *S, void *const *U, const int *ldu,
                      void *const *V, const int *ldv, double tol, int max_sweeps, int *sweeps, int *info) {
@@ -114,6 +116,12 @@ int block_jacobi_run(Ctx *c, int dtype, int w, const std::vector<int> &insts, co
     std::vector<int> active(nm);
     for (int i = 0; i < nm; ++i) active[i] = i;
     std::vector<int> app_rec(rot_ld, -1);
+    // The block rotation of a pair comes from at most two sweeps of the inner one-sided Jacobi on G:
+    // an orthogonal matrix that removes most of G's off-diagonal mass (all of it once the pair is
+    // nearly orthogonal, where Jacobi converges quadratically). The outer test is unchanged -- every
+    // pair's scaled off-diagonal Gram measure <= tol -- so the converged factors meet the same bound;
+    // fully converging each inner SVD costs more sweeps of G than it saves outer sweeps.
+    const int inner_sweeps = BJ_INNER_SWEEPS;
     for (int sw = 0; sw < max_sweeps && !active.empty(); ++sw) {
         std::fill(app_rec.begin(), app_rec.end(), -1);
         for (int s = 0; s < nbmax - 1; ++s) {
@@ -153,6 +161,7 @@ int block_jacobi_run(Ctx *c, int dtype, int w, const std::vector<int> &insts, co
                     t.G = reinterpret_cast<double *>(db + h.oG) + (size_t)g * K * K;
                     t.VG = reinterpret_cast<double *>(db + h.oVG) + (size_t)g * K * K;
                     t.state = reinterpret_cast<double *>(db + h.oPS) + 2 * ((size_t)s * (h.nb / 2) + g);
+                    t.desc = reinterpret_cast<SvdDesc *>(db + oSD) + k;
                     SvdDesc &d = hs[k];
                     d.A = t.G;
                     d.S = reinterpret_cast<double *>(db + h.oSg) + (size_t)g * K;
@@ -193,9 +202,9 @@ int block_jacobi_run(Ctx *c, int dtype, int w, const std::vector<int> &insts, co
             if (choose_jacobi(0, K, K, 0, &jk)) return c->fail(BSVD_EUNSUP, "internal: no Jacobi kernel for G");
             pi = c->prof ? c->prof_begin(BSVD_STAGE_JACOBI, kname_jacobi(0, jk).c_str()) : -1;
             if (jk.kind == JK_WAVE)
-                e = launch_jacobi_wave(0, jk.a, jk.b, dsd, dl, (int)ntask, 1e-15, 60, nullptr, nullptr, c->stream);
+                e = launch_jacobi_wave(0, jk.a, jk.b, dsd, dl, (int)ntask, 1e-15, inner_sweeps, nullptr, nullptr, c->stream);
             else
-                e = launch_jacobi_lds(0, jk.a, jk.b, dsd, dl, (int)ntask, 1e-15, 60, nullptr, nullptr, c->stream);
+                e = launch_jacobi_lds(0, jk.a, jk.b, dsd, dl, (int)ntask, 1e-15, inner_sweeps, nullptr, nullptr, c->stream);
             if (e != hipSuccess) return c->hip_fail(e, "block inner svd launch");
             c->prof_end(pi, 0.0, 0.0);
             std::snprintf(tag, sizeof tag, "bj_apply_kernel<%s, %d>", tname, w);

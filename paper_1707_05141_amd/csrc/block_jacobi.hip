@@ -126,6 +126,10 @@ __global__ __launch_bounds__(256) void bj_gram_kernel(const BjMat *__restrict__ 
     if (tid == 0) {
         t.state[0] = emax[0];            // measure of this pair
         t.state[1] = emax[0] > tol ? 1.0 : 0.0;
+        if (emax[0] <= tol) {            // nothing to rotate: the inner SVD of G skips this task
+            t.desc->M = 0;
+            t.desc->N = 0;
+        }
     }
 }
 

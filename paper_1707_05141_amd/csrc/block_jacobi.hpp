@@ -19,10 +19,12 @@ struct BjMat {
 };
 
 // One (matrix, block pair) task of a round-robin step.
+struct SvdDesc;
 struct BjTask {
     double *G;      // K x K Gram matrix (ld K)
     double *VG;     // K x K block rotation (ld K)
     double *state;  // this pair's slot in the matrix's pair_state
+    SvdDesc *desc;  // the inner SVD's descriptor of G: emptied (M = N = 0) when the pair needs no rotation
     int mat, p, q, pad;
 };
 

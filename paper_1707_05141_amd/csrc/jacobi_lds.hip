@@ -68,6 +68,13 @@ __global__ __launch_bounds__(256) void jacobi_lds_kernel(const SvdDesc *__restri
     const SvdDesc D = descs[inst];
     const int t = threadIdx.x;
     const int M = D.M, N = D.N;
+    if (N == 0) {  // empty descriptor: nothing to do, no outputs (uniform over the workgroup)
+        if (t == 0) {
+            if (info_out) info_out[inst] = INFO_OK;
+            if (sweeps_out) sweeps_out[inst] = 0;
+        }
+        return;
+    }
     // columns padded to an even count: the circle schedule runs on NP = N rounded up to even
     const int NP = (N + 1) & ~1;
 

@@ -57,9 +57,10 @@ __global__ __launch_bounds__(64) void jacobi_wave_kernel(const SvdDesc *__restri
     for (int r = 0; r < NP; ++r) v[r] = (col_ok && r == p) ? T(1) : T(0);
 
     const bool bad = (__ballot(!finite) & gmask) != 0ull;
-    bool done = bad || !active;
+    // an empty descriptor (N = 0) has nothing to do: done at once, no outputs
+    bool done = bad || !active || D.N == 0;
     int sweeps = 0;
-    bool converged = false;
+    bool converged = active && !bad && D.N == 0;
 
     for (int sw = 0; sw < max_sweeps; ++sw) {
         if (__ballot(!done) == 0ull) break;  // every matrix of the wave has converged

@@ -47,7 +47,9 @@ def test_block_graded_512x256(w):
         # accumulated block rotations: orthogonality to c * n * m * u in Frobenius norm
         assert np.linalg.norm(V[b].T @ V[b] - np.eye(256)) <= 1e-10
         assert np.linalg.norm(A[b] - (U[b] * S[b]) @ V[b].T) <= 1e-11 * np.linalg.norm(A[b])
-        assert 3 <= sw[b] <= 20
+        # block rotations from two inner sweeps of G: a few more outer sweeps than with fully
+        # converged inner SVDs on this graded spectrum (about 20 at w = 8, 16 at w = 16)
+        assert 3 <= sw[b] <= 26
     print("block sweeps", sw)
 
 
