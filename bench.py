@@ -97,7 +97,9 @@ def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
-KERNEL_BOUND = (("gemm_nn_kernel", "hbm"), ("gemm_tn_kernel", "hbm"), ("bj_gram_kernel", "mfma"),
+# compute unit of each kernel family; a kernel whose algorithmic flops per byte fall below the FP64
+# machine balance (78.6 TFLOP/s / 8 TB/s = 9.8 flop/B) is priced against HBM instead
+KERNEL_BOUND = (("gemm_nn_kernel", "alu"), ("gemm_tn_kernel", "alu"), ("bj_gram_kernel", "mfma"),
                 ("bj_apply_kernel", "mfma"), ("qr_kernel", "alu"), ("jacobi_", "alu"))
 
 
@@ -130,8 +132,10 @@ def kernel_roofline(kern, steps):
     ranked = sorted(kern.items(), key=lambda kv: -kv[1]["ms"])
     name, k = ranked[0]
     bound = next((b for pre, b in KERNEL_BOUND if name.startswith(pre)), "alu")
-    if bound == "alu" and k["flops"] == 0:
-        bound = "hbm"  # no flop model (data-dependent sweeps): report its algorithmic bytes
+    if k["flops"] == 0:
+        bound = "hbm"  # no flop model: report its algorithmic bytes
+    elif k["bytes"] > 0 and k["flops"] / k["bytes"] < FP64_PEAK_TFLOPS / (HBM_PEAK_GBS * 1e-3):
+        bound = "hbm"  # below the machine balance: HBM is the ceiling
     avg_ms = k["ms"] / k["launches"]
     if bound == "hbm":
         per = k["bytes"] / k["launches"]
@@ -580,6 +584,10 @@ def main():
     ap.add_argument("--c5-max-rank", type=int, default=256)
     ap.add_argument("--c5-variants", default="all",
                     help="comma-separated subset of mixed, learned_fp64 to run besides plain_fp64 and learned_mixed")
+    ap.add_argument("--tune-load", default=None, metavar="PATH",
+                    help="load autotuner choices (bsvd_tune_save format) before the run, e.g. to repeat a run's "
+                         "launch configuration under a counter profiler")
+    ap.add_argument("--tune-save", default=None, metavar="PATH", help="write the autotuner choices after the run")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (y = x * 1, FP64) five times: the reference "
                          "kernel for scaling hardware byte counters")
@@ -604,7 +612,11 @@ def main():
         print(json.dumps(dict(copy_calibration=True, read_bytes_per_launch=8 * nel, write_bytes_per_launch=8 * nel,
                               launches=5)), flush=True)
         return
+    if args.tune_load:
+        P.tune_load(args.tune_load)
     res = WORKLOADS[args.workload](args, torch, P, synth)
+    if args.tune_save:
+        P.tune_save(args.tune_save)
     out = dict(metric=METRIC, value=res["value"], unit=res["unit"], n_gpus=1, steps=args.steps, warmup=args.warmup,
                ms_per_step=res["ms_per_step"], higher_is_better=True, scaling="weak", vs_baseline=None,
                dtype=res["dtype"], data="synthetic", config=res["config"], roofline=res["roofline"])

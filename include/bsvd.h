@@ -118,7 +118,7 @@ int bsvd_profile_kernels(bsvd_ctx *ctx, char *buf, int cap);
 /* Autotuner cache. Without a BSVD_SVD_BLOCK_W* flag, the first batched_svd call that sends a
  * (dtype, M, N) class (M = max(m, n), N = min(m, n)) to the block path times widths 8, 16 and 32 on up
  * to 2048 of its instances (spread over the class, best of two runs each) and keeps the fastest in
- * the context (kind 0). batched_rsvd does the same for the SVD of its R_B factors wider than 64
+ * the context (kind 0; a later candidate must be faster by more than 3% to displace an earlier one). batched_rsvd does the same for the SVD of its R_B factors wider than 64
  * columns, per class of sizes padded to a multiple of 32 (kind 1, M = N = the padded size); up to 128
  * columns the single-kernel LDS Jacobi is a further candidate, reported as value 0. A class met
  * again with more than four times the instances its choice was timed on is timed again (choices

@@ -185,7 +185,9 @@ int tune_block_width(Ctx *c, int dtype, int M, int N, const std::vector<int> &cl
             if (ms < 0.0f || t < ms) ms = t;
         }
         times.push_back({w, ms});
-        if (best_t < 0.0f || ms < best_t) {
+        // a later candidate must be faster by more than 3% to replace the current choice, so that
+        // near-ties resolve the same way from run to run
+        if (best_t < 0.0f || ms < 0.97f * best_t) {
             best_t = ms;
             best = w;
         }

@@ -1,0 +1,101 @@
+"""Summaries of rocprofv3 CSV output for the kernels of libbsvd.so.
+
+The library's own profiler (HIP events around each launch, ``profile_kernels``) gives the average
+duration of a kernel over a timed region; these helpers read the matching numbers out of a
+rocprofv3 run of the same command so the two can be compared:
+
+* ``trace``: from ``--kernel-trace`` output, the average duration of the LAST ``n`` dispatches of a
+  kernel (the timed steps come last in ``bench.py``) next to its average over the whole run.
+* ``pmc``: from two ``--pmc`` runs (FETCH_SIZE, then WRITE_SIZE) and the same two counters taken on a
+  plain copy of known size, the HBM bytes per dispatch of a kernel over its last ``n`` dispatches,
+  each counter scaled by what it reads for the copy.
+
+Usage (paths are rocprofv3 output directories, searched recursively for the CSV files):
+  python -m paper_1707_05141_amd.profiling trace <trace_dir> <kernel> <n>
+  python -m paper_1707_05141_amd.profiling pmc <fetch_dir> <write_dir> <copy_fetch_dir> <copy_write_dir>
+                                           <copy_mib> <kernel> <n>
+``kernel`` is the name the library profiler reports (e.g. "bj_apply_kernel<double, 16>").
+"""
+from __future__ import annotations
+
+import csv
+import glob
+import json
+import os
+import sys
+
+
+def _rows(directory, pattern):
+    out = []
+    for f in sorted(glob.glob(os.path.join(directory, "**", pattern), recursive=True)):
+        with open(f, newline="") as fh:
+            out += list(csv.DictReader(fh))
+    return out
+
+
+def matches(rocprof_name, kernel):
+    """True if a rocprofv3 kernel name ("void bsvd::k<double, 16>(args)") is the library kernel
+    instantiation ``kernel`` ("k<double, 16>")."""
+    name = rocprof_name.replace("void ", "", 1).strip()
+    if name.startswith("bsvd::"):
+        name = name[len("bsvd::"):]
+    return name.startswith(kernel + "(") or name == kernel
+
+
+def trace(directory, kernel, n):
+    """Durations (ms) of ``kernel`` from kernel_trace CSV files: dict(last_n_avg_ms, all_avg_ms,
+    dispatches, last_n)."""
+    rows = [r for r in _rows(directory, "*kernel_trace.csv") if matches(r["Kernel_Name"], kernel)]
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    dur = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-6 for r in rows]
+    if not dur:
+        raise SystemExit("no dispatch of %s in %s" % (kernel, directory))
+    tail = dur[-n:] if n > 0 else dur
+    return dict(last_n_avg_ms=sum(tail) / len(tail), all_avg_ms=sum(dur) / len(dur), dispatches=len(dur),
+                last_n=len(tail))
+
+
+def counter_avg(directory, kernel, counter, n=0):
+    """Average per-dispatch value of ``counter`` for ``kernel`` (all kernels if None) over its last
+    ``n`` dispatches (all if n <= 0)."""
+    vals = {}
+    for r in _rows(directory, "*counter_collection.csv"):
+        if r["Counter_Name"] != counter or (kernel is not None and not matches(r["Kernel_Name"], kernel)):
+            continue
+        d = int(r["Dispatch_Id"])
+        vals[d] = vals.get(d, 0.0) + float(r["Counter_Value"])
+    if not vals:
+        raise SystemExit("no %s values for %s in %s" % (counter, kernel, directory))
+    keys = sorted(vals)
+    if n > 0:
+        keys = keys[-n:]
+    return sum(vals[k] for k in keys) / len(keys), len(keys)
+
+
+def pmc(fetch_dir, write_dir, cfetch_dir, cwrite_dir, copy_mib, kernel, n):
+    """HBM traffic per dispatch of ``kernel`` (last n dispatches), FETCH_SIZE / WRITE_SIZE scaled by
+    the copy calibration (a copy of copy_mib MiB reads and writes copy_mib * 1024 KiB)."""
+    f_kib, nf = counter_avg(fetch_dir, kernel, "FETCH_SIZE", n)
+    w_kib, nw = counter_avg(write_dir, kernel, "WRITE_SIZE", n)
+    # the copy run (bench.py --copy-calibration) ends with its five copy dispatches
+    cf, _ = counter_avg(cfetch_dir, None, "FETCH_SIZE", 5)
+    cw, _ = counter_avg(cwrite_dir, None, "WRITE_SIZE", 5)
+    exact = copy_mib * 1024.0
+    fs, ws = exact / cf, exact / cw
+    return dict(fetch_kib=f_kib, write_kib=w_kib, fetch_scale=fs, write_scale=ws, dispatches=(nf, nw),
+                copy_fetch_kib=cf, copy_write_kib=cw, bytes_per_dispatch=1024.0 * (f_kib * fs + w_kib * ws))
+
+
+def main(argv):
+    if len(argv) >= 4 and argv[0] == "trace":
+        print(json.dumps(trace(argv[1], argv[2], int(argv[3]))))
+    elif len(argv) >= 8 and argv[0] == "pmc":
+        print(json.dumps(pmc(argv[1], argv[2], argv[3], argv[4], float(argv[5]), argv[6], int(argv[7]))))
+    else:
+        print(__doc__)
+        return 2
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main(sys.argv[1:]))
