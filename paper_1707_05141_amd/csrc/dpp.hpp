@@ -1,0 +1,43 @@
+// Cross-lane moves inside rows of 16 lanes (DPP) and group sums built on them.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace bsvd {
+
+// Value of the lane selected by the DPP control CTRL (quad_perm, row_mirror, row_half_mirror, ...);
+// every lane must be active.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double x) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float x) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL, 0xF, 0xF, false));
+}
+
+constexpr int DPP_XOR1 = 1 | (0 << 2) | (3 << 4) | (2 << 6);  // quad_perm [1, 0, 3, 2]
+constexpr int DPP_XOR2 = 2 | (3 << 2) | (0 << 4) | (1 << 6);  // quad_perm [2, 3, 0, 1]
+constexpr int DPP_ROW_MIRROR = 0x140;                         // lane i <- 15 - i (in a row of 16)
+constexpr int DPP_ROW_HALF_MIRROR = 0x141;                    // lane i <- 7 - i (in a half row)
+
+// Sum over aligned groups of G lanes (G a power of two <= 64), the same bits in every lane of the
+// group. Up to 16 lanes the partial sums move by DPP (no trip through the LDS crossbar): mirror
+// folds first (lane i adds lane 15 - i, then 7 - i), then the quad exchanges; every lane adds the same
+// two values at each level, in the same order as its partner. Wider groups finish with shuffles.
+template <int G, typename T>
+__device__ __forceinline__ T group_sum(T v) {
+    static_assert(G >= 1 && G <= 64 && (G & (G - 1)) == 0, "power-of-two group");
+    if constexpr (G >= 16) v += dpp_move<DPP_ROW_MIRROR>(v);
+    if constexpr (G >= 8) v += dpp_move<DPP_ROW_HALF_MIRROR>(v);
+    if constexpr (G >= 2) v += dpp_move<DPP_XOR1>(v);
+    if constexpr (G >= 4) v += dpp_move<DPP_XOR2>(v);
+    if constexpr (G >= 32) v += __shfl_xor(v, 16, 64);
+    if constexpr (G >= 64) v += __shfl_xor(v, 32, 64);
+    return v;
+}
+
+}  // namespace bsvd

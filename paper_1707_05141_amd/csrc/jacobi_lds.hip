@@ -12,37 +12,14 @@
 // Precision: T = double, or T = float with dot products, norms, angle and test in double.
 
 #include "common.hpp"
+#include "dpp.hpp"
 #include "jacobi_device.hpp"
 
 namespace bsvd {
 
-// Lane moves of a double inside rows of 16 lanes (DPP): the control selects the source lane.
-template <int CTRL>
-__device__ __forceinline__ double dpp_d(double x) {
-    const unsigned long long b = __builtin_bit_cast(unsigned long long, x);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
-    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
-}
-constexpr int DPP_XOR1 = 1 | (0 << 2) | (3 << 4) | (2 << 6);  // quad_perm [1, 0, 3, 2]
-constexpr int DPP_XOR2 = 2 | (3 << 2) | (0 << 4) | (1 << 6);  // quad_perm [2, 3, 0, 1]
-constexpr int DPP_ROW_MIRROR = 0x140;                         // lane i <- 15 - i (in a row of 16)
-constexpr int DPP_ROW_HALF_MIRROR = 0x141;                    // lane i <- 7 - i (in a half row)
-
-// Sum over aligned groups of LPP lanes, the same bits in every lane of the group. Up to 16 lanes
-// the partial sums move by DPP (no trip through the LDS crossbar): mirror folds first (lane i adds
-// lane 15 - i, then 7 - i), then the quad exchanges; every lane adds the same two values at each
-// level, in the same order as its partner. Wider groups finish with shuffles.
 template <int LPP>
 __device__ __forceinline__ double grp_sum(double v) {
-    static_assert(LPP >= 1 && LPP <= 64 && (LPP & (LPP - 1)) == 0, "power-of-two group");
-    if constexpr (LPP >= 16) v += dpp_d<DPP_ROW_MIRROR>(v);
-    if constexpr (LPP >= 8) v += dpp_d<DPP_ROW_HALF_MIRROR>(v);
-    if constexpr (LPP >= 2) v += dpp_d<DPP_XOR1>(v);
-    if constexpr (LPP >= 4) v += dpp_d<DPP_XOR2>(v);
-    if constexpr (LPP >= 32) v += __shfl_xor(v, 16, 64);
-    if constexpr (LPP >= 64) v += __shfl_xor(v, 32, 64);
-    return v;
+    return group_sum<LPP>(v);
 }
 
 template <typename T, int MMAX, int NMAX>
@@ -357,7 +334,7 @@ __global__ __launch_bounds__(512) void jacobi_lds_wide_kernel(const SvdDesc *__r
 // as a DPP quad_perm control.
 template <int CTRL>
 __device__ __forceinline__ double quad_perm(double x) {
-    return dpp_d<CTRL>(x);
+    return dpp_move<CTRL>(x);
 }
 constexpr int QP_NEXT = 1 | (2 << 2) | (3 << 4) | (0 << 6);  // from lane a + 1 (mod 4)
 constexpr int QP_PREV = 3 | (0 << 2) | (1 << 4) | (2 << 6);  // from lane a - 1 (mod 4)

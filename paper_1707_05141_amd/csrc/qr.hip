@@ -15,14 +15,13 @@
 // is exactly zero, or of length one, gets H = I.
 
 #include "common.hpp"
+#include "dpp.hpp"
 
 namespace bsvd {
 
 template <typename T, int SEG>
 __device__ __forceinline__ T seg_sum(T v) {
-#pragma unroll
-    for (int o = SEG / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    return group_sum<SEG>(v);
 }
 
 template <typename T, int NB, int SEG, int KR>
