@@ -103,10 +103,13 @@ KERNEL_BOUND = (("gemm_nn_kernel", "alu"), ("gemm_tn_kernel", "alu"), ("bj_gram_
                 ("bj_apply_kernel", "mfma"), ("qr_kernel", "alu"), ("jacobi_", "alu"))
 
 
-def pmc_traffic(kernel):
+def pmc_traffic(kernel, alg_bytes=None):
     """HBM bytes per launch of `kernel` from a committed PMC summary under profiles/ (a line
-    "traffic: kernel=... fetch_kib=... fetch_scale=... write_kib=... write_scale=... source=... sha1=..."),
-    or None if there is none or the kernel's source file has changed since the counters were taken."""
+    "traffic: kernel=... fetch_kib=... fetch_scale=... write_kib=... write_scale=... alg_bytes=...
+    source=... sha1=..."), as (bytes, bytes / algorithmic bytes of the profiled launches). The bytes are
+    None if there is no such line, if the kernel's source file has changed since the counters were
+    taken, or if this run's algorithmic bytes per launch differ by more than 2% from the profiled
+    run's (another launch mix, e.g. other autotuner choices); the ratio is kept in that last case."""
     import glob
     import hashlib
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
@@ -120,10 +123,15 @@ def pmc_traffic(kernel):
                 continue
             src = os.path.join(ROOT, fields["source"])
             if not os.path.exists(src) or hashlib.sha1(open(src, "rb").read()).hexdigest() != fields["sha1"]:
-                return None
-            return 1024.0 * (float(fields["fetch_kib"]) * float(fields["fetch_scale"]) +
-                             float(fields["write_kib"]) * float(fields["write_scale"]))
-    return None
+                return None, None
+            measured = 1024.0 * (float(fields["fetch_kib"]) * float(fields["fetch_scale"]) +
+                                 float(fields["write_kib"]) * float(fields["write_scale"]))
+            prof_alg = float(fields["alg_bytes"])
+            ratio = measured / prof_alg
+            if alg_bytes is not None and abs(alg_bytes / prof_alg - 1.0) > 0.02:
+                return None, ratio
+            return measured, ratio
+    return None, None
 
 
 def kernel_roofline(kern, steps):
@@ -145,7 +153,9 @@ def kernel_roofline(kern, steps):
         ach = per / (avg_ms * 1e-3) / 1e12
         peak = FP64_PEAK_TFLOPS if bound == "alu" else FP64_PEAK_TFLOPS
         unit = "TFLOP/s"
-    roof = dict(bound=bound, achieved=ach, peak=peak, unit=unit, frac=ach / peak, traffic=pmc_traffic(name), kernel=name,
+    traffic, ratio = pmc_traffic(name, k["bytes"] / k["launches"])
+    roof = dict(bound=bound, achieved=ach, peak=peak, unit=unit, frac=ach / peak, traffic=traffic,
+                traffic_over_algorithmic_at_profile=ratio, kernel=name,
                 kernel_avg_ms=avg_ms, launches_per_step=k["launches"] / steps,
                 algorithmic_per_launch=per, algorithmic_unit="bytes" if bound == "hbm" else "flops",
                 algorithmic_bytes_per_launch=k["bytes"] / k["launches"], traffic_unit="bytes per launch")
