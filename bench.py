@@ -160,7 +160,8 @@ def kernel_roofline(kern, steps):
                 algorithmic_per_launch=per, algorithmic_unit="bytes" if bound == "hbm" else "flops",
                 algorithmic_bytes_per_launch=k["bytes"] / k["launches"], traffic_unit="bytes per launch")
     table = [dict(kernel=n, stage=v["stage"], ms_per_step=v["ms"] / steps, launches_per_step=v["launches"] / steps,
-                  avg_ms=v["ms"] / v["launches"]) for n, v in ranked[:10]]
+                  avg_ms=v["ms"] / v["launches"], algorithmic_gb_per_s=v["bytes"] / (v["ms"] * 1e-3) / 1e9,
+                  algorithmic_tflop_per_s=v["flops"] / (v["ms"] * 1e-3) / 1e12) for n, v in ranked[:12]]
     return roof, table
 
 

@@ -92,6 +92,8 @@ inline std::string kname_gemm(int kind, int nmax) {
     char b[96];
     if (kind == 1)
         std::snprintf(b, sizeof b, "gemm_tn_kernel<%d>", nmax);
+    else if (kind == 0 && nmax >= 16)
+        std::snprintf(b, sizeof b, "gemm_nn_mfma_kernel<%d>", nmax);  // FP64, 16..64 outputs: matrix cores
     else
         std::snprintf(b, sizeof b, "gemm_nn_kernel<%d, %s>", nmax, kind == 2 ? "float" : "double");
     return b;

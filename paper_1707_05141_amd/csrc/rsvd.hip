@@ -123,7 +123,9 @@ __device__ __forceinline__ double dd_sum_pairs(const double *p, int n) {
 // ---------------------------------------------------------------------------------------------
 template <int NMAX, typename TA = double>
 __global__ __launch_bounds__(64) void gemm_nn_kernel(const MMDesc *__restrict__ d, const int2 *__restrict__ tiles) {
-    constexpr int KC = 64;
+    // k chunk staged in LDS: 16 KB per workgroup at most, so that LDS does not cap the number of
+    // resident waves below what the registers allow
+    constexpr int KC = NMAX * (int)sizeof(TA) * 64 > 16384 ? 16384 / (NMAX * (int)sizeof(TA)) : 64;
     __shared__ TA ys[KC * NMAX];
     const int2 tl = tiles[blockIdx.x];
     const MMDesc D = d[tl.x];
@@ -147,26 +149,33 @@ __global__ __launch_bounds__(64) void gemm_nn_kernel(const MMDesc *__restrict__ 
         __syncthreads();
         if (rok) {
             const double *xp = D.X + r + (size_t)k0 * D.ldx;
-            int kk = 0;
-            for (; kk + 4 <= kc; kk += 4) {
-                const double x0 = xp[(size_t)(kk + 0) * D.ldx];
-                const double x1 = xp[(size_t)(kk + 1) * D.ldx];
-                const double x2 = xp[(size_t)(kk + 2) * D.ldx];
-                const double x3 = xp[(size_t)(kk + 3) * D.ldx];
-                if (wantx) {
-                    dd_add_sq(xs, xl, x0);
-                    dd_add_sq(xs, xl, x1);
-                    dd_add_sq(xs, xl, x2);
-                    dd_add_sq(xs, xl, x3);
-                }
-                const TA y0 = (TA)x0, y1 = (TA)x1, y2 = (TA)x2, y3 = (TA)x3;
+            // groups of PF entries of the row, the next group's loads in flight while the current
+            // group's products run
+            constexpr int PF = 8;
+            const int kg = kc - kc % PF;
+            double xa[PF], xb[PF];
+            if (kg > 0) {
 #pragma unroll
-                for (int j = 0; j < NMAX; ++j) {
-                    acc[j] = fma(y0, ys[(kk + 0) * NMAX + j], acc[j]);
-                    acc[j] = fma(y1, ys[(kk + 1) * NMAX + j], acc[j]);
-                    acc[j] = fma(y2, ys[(kk + 2) * NMAX + j], acc[j]);
-                    acc[j] = fma(y3, ys[(kk + 3) * NMAX + j], acc[j]);
+                for (int u = 0; u < PF; ++u) xa[u] = xp[(size_t)u * D.ldx];
+            }
+            int kk = 0;
+            for (; kk < kg; kk += PF) {
+                if (kk + PF < kg) {
+#pragma unroll
+                    for (int u = 0; u < PF; ++u) xb[u] = xp[(size_t)(kk + PF + u) * D.ldx];
                 }
+                if (wantx) {
+#pragma unroll
+                    for (int u = 0; u < PF; ++u) dd_add_sq(xs, xl, xa[u]);
+                }
+#pragma unroll
+                for (int u = 0; u < PF; ++u) {
+                    const TA y = (TA)xa[u];
+#pragma unroll
+                    for (int j = 0; j < NMAX; ++j) acc[j] = fma(y, ys[(kk + u) * NMAX + j], acc[j]);
+                }
+#pragma unroll
+                for (int u = 0; u < PF; ++u) xa[u] = xb[u];
             }
             for (; kk < kc; ++kk) {
                 const double x = xp[(size_t)kk * D.ldx];
@@ -205,6 +214,115 @@ __global__ __launch_bounds__(64) void gemm_nn_kernel(const MMDesc *__restrict__ 
 }
 
 // ---------------------------------------------------------------------------------------------
+// FP64 variant of gemm_nn_kernel on the matrix cores, for 16..64 outputs (the sketch of a learned
+// first block, the wide CGS projections and back-transforms: about 2 N flops per byte of X, enough
+// to leave the HBM roof). One wave per 64-row tile; the tile is four 16-row blocks times N / 16
+// column blocks of v_mfma_f64_16x16x4f64 accumulators. Lane l supplies A[l % 16][l / 16] (rows of
+// X, four consecutive k) and B[l / 16][l % 16] (Y, staged in LDS), and holds D[l / 16 + 4 q][l % 16]
+// in item q of an accumulator. The sums of squares (X's entries when D.xsq is set, the outputs' when
+// D.csq is set) cover each entry once per tile, in a fixed order.
+// ---------------------------------------------------------------------------------------------
+typedef double mf_d4 __attribute__((ext_vector_type(4)));
+
+template <int NMAX>
+__global__ __launch_bounds__(64) void gemm_nn_mfma_kernel(const MMDesc *__restrict__ d, const int2 *__restrict__ tiles) {
+    static_assert(NMAX % 16 == 0 && NMAX <= 64, "16..64 outputs");
+    constexpr int NB = NMAX / 16;
+    constexpr int KC = 16384 / (NMAX * 8);  // k rows of Y per LDS chunk (16 KB)
+    __shared__ double ys[KC * NMAX];
+    const int2 tl = tiles[blockIdx.x];
+    const MMDesc D = d[tl.x];
+    const int l = threadIdx.x;
+    const int li = l & 15, lk = l >> 4;
+    const int r0 = tl.y * 64;
+    mf_d4 acc[4][NB];
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < NB; ++cb) acc[rb][cb] = mf_d4{0.0, 0.0, 0.0, 0.0};
+    double xs = 0.0, xl = 0.0;
+    const bool wantx = D.xsq != nullptr;
+    const double *Yp = static_cast<const double *>(D.Y);
+    for (int k0 = 0; k0 < D.K; k0 += KC) {
+        const int kc = (D.K - k0) < KC ? (D.K - k0) : KC;
+        for (int idx = l; idx < KC * NMAX; idx += 64) {
+            const int kk = idx / NMAX, j = idx - (idx / NMAX) * NMAX;
+            double y = 0.0;
+            if (kk < kc && j < D.N) y = D.ytrans ? Yp[(size_t)(k0 + kk) * D.ldy + j] : Yp[(k0 + kk) + (size_t)j * D.ldy];
+            ys[idx] = y;
+        }
+        __syncthreads();
+        // groups of G k-steps (4 k each): the next group's X fragments are loaded while the current
+        // group's products run
+        constexpr int G = 4;
+        double a[G][4], an[G][4];
+        auto load_group = [&](int kg, double (&dst)[G][4]) {
+#pragma unroll
+            for (int g = 0; g < G; ++g)
+#pragma unroll
+                for (int rb = 0; rb < 4; ++rb) {
+                    const int kk = kg + 4 * g + lk;
+                    const int r = r0 + 16 * rb + li;
+                    dst[g][rb] = (r < D.M && kk < kc) ? D.X[r + (size_t)(k0 + kk) * D.ldx] : 0.0;
+                }
+        };
+        load_group(0, a);
+        for (int kg = 0; kg < kc; kg += 4 * G) {
+            if (kg + 4 * G < kc) load_group(kg + 4 * G, an);
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                const int kk = kg + 4 * g;
+                if (kk < kc) {
+                    if (wantx) {
+#pragma unroll
+                        for (int rb = 0; rb < 4; ++rb) dd_add_sq(xs, xl, a[g][rb]);
+                    }
+#pragma unroll
+                    for (int cb = 0; cb < NB; ++cb) {
+                        const double b = ys[(kk + lk) * NMAX + 16 * cb + li];  // zero past kc (staged zeros)
+#pragma unroll
+                        for (int rb = 0; rb < 4; ++rb)
+                            acc[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[g][rb], b, acc[rb][cb], 0, 0, 0);
+                    }
+                }
+            }
+#pragma unroll
+            for (int g = 0; g < G; ++g)
+#pragma unroll
+                for (int rb = 0; rb < 4; ++rb) a[g][rb] = an[g][rb];
+        }
+        __syncthreads();
+    }
+    double cs = 0.0;
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < NB; ++cb)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int r = r0 + 16 * rb + lk + 4 * q;
+                const int j = 16 * cb + li;
+                if (r < D.M && j < D.N) {
+                    double *cp = D.C + r + (size_t)j * D.ldc;
+                    const double v = D.beta != 0.0 ? fma(D.alpha, acc[rb][cb][q], D.beta * (*cp)) : D.alpha * acc[rb][cb][q];
+                    *cp = v;
+                    cs = fma(v, v, cs);
+                }
+            }
+    if (wantx) {
+        wave_sum_dd(xs, xl);
+        if (l == 0) {
+            D.xsq[2 * tl.y] = xs;
+            D.xsq[2 * tl.y + 1] = xl;
+        }
+    }
+    if (D.csq) {
+        cs = wave_sum(cs);
+        if (l == 0) D.csq[tl.y] = cs;
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
 // C (K x N) = alpha X^T Y + beta C, X column-major M x K, Y column-major M x N, C column-major K x N.
 // One 256-thread workgroup per 64 columns of X. Row chunks of the X tile are loaded coalesced
 // (consecutive lanes read consecutive rows of a column) into LDS transposed, together with the
@@ -229,23 +347,43 @@ __global__ __launch_bounds__(256) void gemm_tn_kernel(const MMDesc *__restrict__
     double acc[NJ];
 #pragma unroll
     for (int j = 0; j < NJ; ++j) acc[j] = 0.0;
-    for (int r0 = 0; r0 < D.M; r0 += RC) {
+    // the next chunk's X and Y entries are loaded into registers while the current chunk is used
+    // (up to 64 outputs per column; the wide variants keep their registers for the accumulators)
+    constexpr bool PIPE = NMAX <= 64;
+    constexpr int XL = (RC * 64) / 256, YL = (RC * NMAX + 255) / 256;
+    const double *Yp = static_cast<const double *>(D.Y);
+    double xr[XL], yr[YL];
+    auto load_chunk = [&](int r0) {
         const int rc = (D.M - r0) < RC ? (D.M - r0) : RC;
 #pragma unroll
-        for (int i = 0; i < (RC * 64) / 256; ++i) {
+        for (int i = 0; i < XL; ++i) {
             const int idx = t + 256 * i;
             const int cc = idx / RC, rr = idx - (idx / RC) * RC;
-            double v = 0.0;
-            if (rr < rc && c0 + cc < D.K) v = D.X[(r0 + rr) + (size_t)(c0 + cc) * D.ldx];
-            xs[rr][cc] = v;
+            xr[i] = (rr < rc && c0 + cc < D.K) ? D.X[(r0 + rr) + (size_t)(c0 + cc) * D.ldx] : 0.0;
         }
-        for (int idx = t; idx < RC * NMAX; idx += 256) {
+#pragma unroll
+        for (int i = 0; i < YL; ++i) {
+            const int idx = t + 256 * i;
             const int j = idx / RC, rr = idx - (idx / RC) * RC;
-            double v = 0.0;
-            if (j < D.N && rr < rc) v = static_cast<const double *>(D.Y)[(r0 + rr) + (size_t)j * D.ldy];
-            ys[rr][j] = v;
+            yr[i] = (idx < RC * NMAX && j < D.N && rr < rc) ? Yp[(r0 + rr) + (size_t)j * D.ldy] : 0.0;
+        }
+    };
+    if (PIPE && D.M > 0) load_chunk(0);
+    for (int r0 = 0; r0 < D.M; r0 += RC) {
+        const int rc = (D.M - r0) < RC ? (D.M - r0) : RC;
+        if (!PIPE) load_chunk(r0);
+#pragma unroll
+        for (int i = 0; i < XL; ++i) {
+            const int idx = t + 256 * i;
+            xs[idx - (idx / RC) * RC][idx / RC] = xr[i];
+        }
+#pragma unroll
+        for (int i = 0; i < YL; ++i) {
+            const int idx = t + 256 * i;
+            if (idx < RC * NMAX) ys[idx - (idx / RC) * RC][idx / RC] = yr[i];
         }
         __syncthreads();
+        if (PIPE && r0 + RC < D.M) load_chunk(r0 + RC);
         for (int rr = 0; rr < rc; ++rr) {
             const double x = xs[rr][c];
 #pragma unroll
@@ -452,9 +590,9 @@ hipError_t launch_gemm_nn(int nmax, const MMDesc *d, const int2 *tiles, int ntil
     if (ntiles <= 0) return hipSuccess;
     switch (nmax) {
         case 8: hipLaunchKernelGGL(gemm_nn_kernel<8>, dim3(ntiles), dim3(64), 0, st, d, tiles); break;
-        case 16: hipLaunchKernelGGL(gemm_nn_kernel<16>, dim3(ntiles), dim3(64), 0, st, d, tiles); break;
-        case 32: hipLaunchKernelGGL(gemm_nn_kernel<32>, dim3(ntiles), dim3(64), 0, st, d, tiles); break;
-        case 64: hipLaunchKernelGGL(gemm_nn_kernel<64>, dim3(ntiles), dim3(64), 0, st, d, tiles); break;
+        case 16: hipLaunchKernelGGL(gemm_nn_mfma_kernel<16>, dim3(ntiles), dim3(64), 0, st, d, tiles); break;
+        case 32: hipLaunchKernelGGL(gemm_nn_mfma_kernel<32>, dim3(ntiles), dim3(64), 0, st, d, tiles); break;
+        case 64: hipLaunchKernelGGL(gemm_nn_mfma_kernel<64>, dim3(ntiles), dim3(64), 0, st, d, tiles); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
