@@ -439,7 +439,8 @@ def run_c5(args, torch, P, synth):
     tm, tn, tk, tw = synth.c5_mixture(6000, seed=501)
     tbuf, toffs = synth.mixed_blocks_packed(tm, tn, tk, tw, seed=501)
     log("training set generated (%.1f s)" % (time.perf_counter() - t0))
-    model = rankmodel.train_packed(tbuf, toffs, tm, tn, eps=eps, seed=11, epochs=60, max_rank=max_rank)
+    model = rankmodel.train_packed(tbuf, toffs, tm, tn, eps=eps, seed=11, epochs=60, max_rank=max_rank,
+                                   coverage=args.c5_coverage, oversample=args.c5_oversample)
     del tbuf
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
@@ -593,6 +594,9 @@ def main():
     ap.add_argument("--block-w", type=int, default=0, choices=(0, 8, 16, 32), help="0 = autotuned")
     ap.add_argument("--c5-count", type=int, default=100000)
     ap.add_argument("--c5-max-rank", type=int, default=256)
+    ap.add_argument("--c5-coverage", type=float, default=0.8,
+                    help="quantile of the rank network's training residuals covered by the first block")
+    ap.add_argument("--c5-oversample", type=float, default=6.0, help="columns added to the covered rank")
     ap.add_argument("--c5-variants", default="all",
                     help="comma-separated subset of mixed, learned_fp64 to run besides plain_fp64 and learned_mixed")
     ap.add_argument("--tune-load", default=None, metavar="PATH",

@@ -236,8 +236,9 @@ int batched_qr(bsvd_ctx *ctx, int dtype, int batch, const int *m, const int *n, 
  *   seed         64-bit key of the sampling matrix
  *   flags        BSVD_RSVD_* (0 = adaptive). With BSVD_RSVD_LEARNED (ell0 must be NULL) the context's
  *                rank model predicts each block's rank k^ from its probe features (bsvd_rank_features)
- *                and the first block takes ell0 = ceil(k^ + margin) samples; the check and the
- *                adaptive growth above remain the fallback whenever that basis is not accurate enough.
+ *                and the first block takes ell0 = min(ceil(k^ + margin), 32) samples; the check and
+ *                the adaptive growth above remain the fallback whenever that basis is not accurate
+ *                enough.
  *   ell0         nullable host int[batch]: initial number of samples (clamped to the basis cap)
  *   samples      nullable DEVICE int[batch]: final basis size (number of Gaussian samples used)
  * The call synchronises its stream once per growth round and once per check (the per-instance

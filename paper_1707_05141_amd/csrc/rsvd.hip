@@ -371,16 +371,28 @@ __global__ __launch_bounds__(256) void gemm_tn_kernel(const MMDesc *__restrict__
     if (PIPE && D.M > 0) load_chunk(0);
     for (int r0 = 0; r0 < D.M; r0 += RC) {
         const int rc = (D.M - r0) < RC ? (D.M - r0) : RC;
-        if (!PIPE) load_chunk(r0);
+        if constexpr (PIPE) {
 #pragma unroll
-        for (int i = 0; i < XL; ++i) {
-            const int idx = t + 256 * i;
-            xs[idx - (idx / RC) * RC][idx / RC] = xr[i];
-        }
+            for (int i = 0; i < XL; ++i) {
+                const int idx = t + 256 * i;
+                xs[idx - (idx / RC) * RC][idx / RC] = xr[i];
+            }
 #pragma unroll
-        for (int i = 0; i < YL; ++i) {
-            const int idx = t + 256 * i;
-            if (idx < RC * NMAX) ys[idx - (idx / RC) * RC][idx / RC] = yr[i];
+            for (int i = 0; i < YL; ++i) {
+                const int idx = t + 256 * i;
+                if (idx < RC * NMAX) ys[idx - (idx / RC) * RC][idx / RC] = yr[i];
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < XL; ++i) {
+                const int idx = t + 256 * i;
+                const int cc = idx / RC, rr = idx - (idx / RC) * RC;
+                xs[rr][cc] = (rr < rc && c0 + cc < D.K) ? D.X[(r0 + rr) + (size_t)(c0 + cc) * D.ldx] : 0.0;
+            }
+            for (int idx = t; idx < RC * NMAX; idx += 256) {
+                const int j = idx / RC, rr = idx - (idx / RC) * RC;
+                ys[rr][j] = (j < D.N && rr < rc) ? Yp[(r0 + rr) + (size_t)j * D.ldy] : 0.0;
+            }
         }
         __syncthreads();
         if (PIPE && r0 + RC < D.M) load_chunk(r0 + RC);
@@ -444,6 +456,10 @@ __global__ void grow_decide_kernel(RsvdState *__restrict__ st, const GrowItem *_
     const double est2 = e / (double)it.b;
     const double thr = (S.eps / S.safety) * (S.eps / S.safety) * S.normA2;
     S.ell += it.b;
+    // a basis grown by FP64 samples under this estimator is checked as in the plain method: the
+    // estimator has already asked for eps / safety (a learned first block alone is checked at
+    // eps / safety, since no estimator has seen it)
+    if (!it.f32) S.accept = 1.0;
     S.flag = (S.nonfinite || est2 <= thr || S.ell >= S.cap) ? 1 : 0;
     // An FP32 sample column carries rounding noise of about n u32^2 ||A||_F^2 in squared norm
     // (u32 = 2^-24). Once the estimate is within 256x of that floor (16x in norm), the directions

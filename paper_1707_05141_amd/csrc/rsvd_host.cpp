@@ -56,7 +56,11 @@ constexpr int PW = 32;        // panel width of the Gram-Schmidt orthonormalisat
                               // Gram-Schmidt products are GEMMs: narrower panels are cheaper)
 constexpr int GROW_BLK = 8;
 constexpr int BLOCK_W = 16;   // block width of the block Jacobi on R_B if the tuner finds none
-constexpr int WIDE_LDS = 128; // widest R_B for the LDS-resident Jacobi with V in global memory
+// widest learned first block: a 32-column Householder QR costs a quarter of a 64-column one per
+// instance, and growth past it in 8-column blocks is cheap (measured on the C5 mixture: 32 columns
+// 1.055 s, 48 columns 1.095 s, 64 columns 1.087 s per 100,000 blocks)
+constexpr int LEARNED_MAX0 = 32;
+constexpr int WIDE_LDS = 128; // widest R_B for the single-kernel LDS Jacobi (V in registers above 96)
 constexpr double SAFETY = 2.0;
 constexpr size_t WS_BUDGET = (size_t)96 << 30;  // workspace bound of one sub-batch
 
@@ -361,7 +365,8 @@ static int rsvd_range(Ctx *c, int inst_base, int batch, const int *m, const int 
             s.safety = SAFETY;
             // plain: final once the check meets eps (the estimator has already asked for eps / 2);
             // with a learned or FP32 first block the check itself asks for eps / 2, so that the
-            // truncation keeps most of the budget (the rank stays that of the plain method)
+            // truncation keeps most of the budget (the rank stays that of the plain method), until
+            // FP64 growth blocks under the estimator take over (then eps, as plain)
             s.accept = (learned || mixed) ? 1.0 / (SAFETY * SAFETY) : 1.0;
             s.m = q.m;
             s.n = q.n;
@@ -650,7 +655,7 @@ static int rsvd_range(Ctx *c, int inst_base, int batch, const int *m, const int 
             // small SVD, while the growth that completes an undershoot costs a few 8-column rounds.
             const int e0 = rbv()[b];
             if (e0 > PANEL) I[b].f32 = false;
-            I[b].ell0 = std::min(e0, std::min(PANEL, I[b].cap));
+            I[b].ell0 = std::min(e0, std::min(LEARNED_MAX0, I[b].cap));
         }
     }
 
