@@ -601,7 +601,8 @@ def main():
                     help="comma-separated subset of mixed, learned_fp64 to run besides plain_fp64 and learned_mixed")
     ap.add_argument("--tune-load", default=None, metavar="PATH",
                     help="load autotuner choices (bsvd_tune_save format) before the run, e.g. to repeat a run's "
-                         "launch configuration under a counter profiler")
+                         "launch configuration under a counter profiler (default for c5: the shipped "
+                         "paper_1707_05141_amd/tuning/mi355x_rsvd_c5.txt if present; 'none' autotunes)")
     ap.add_argument("--tune-save", default=None, metavar="PATH", help="write the autotuner choices after the run")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (y = x * 1, FP64) five times: the reference "
@@ -627,14 +628,21 @@ def main():
         print(json.dumps(dict(copy_calibration=True, read_bytes_per_launch=8 * nel, write_bytes_per_launch=8 * nel,
                               launches=5)), flush=True)
         return
-    if args.tune_load:
-        P.tune_load(args.tune_load)
+    tune_file = args.tune_load
+    if tune_file is None and args.workload == "c5":
+        shipped = os.path.join(ROOT, "paper_1707_05141_amd", "tuning", "mi355x_rsvd_c5.txt")
+        tune_file = shipped if os.path.exists(shipped) else None
+    if tune_file and tune_file != "none":
+        P.tune_load(tune_file)
+        log("autotuner choices loaded from %s" % tune_file)
     res = WORKLOADS[args.workload](args, torch, P, synth)
     if args.tune_save:
         P.tune_save(args.tune_save)
     out = dict(metric=METRIC, value=res["value"], unit=res["unit"], n_gpus=1, steps=args.steps, warmup=args.warmup,
                ms_per_step=res["ms_per_step"], higher_is_better=True, scaling="weak", vs_baseline=None,
                dtype=res["dtype"], data="synthetic", config=res["config"], roofline=res["roofline"])
+    out["config"]["autotuner"] = ("choices loaded from " + os.path.relpath(tune_file, ROOT)
+                                  if tune_file and tune_file != "none" else "tuned in this run")
     if "cpu_baseline" in res:
         out["cpu_baseline"] = res["cpu_baseline"]
     print(json.dumps(out), flush=True)
