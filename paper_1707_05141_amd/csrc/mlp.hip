@@ -11,6 +11,7 @@
 
 #include "common.hpp"
 #include "mlp.hpp"
+#include "dpp.hpp"
 
 namespace bsvd {
 
@@ -154,51 +155,60 @@ __global__ __launch_bounds__(256) void mlp_loss_kernel(int n, const float *__res
 //   f15 = log2(k ||A||_F^2 / s1^2) / 8 with s1 = ||R v|| after 64 power steps on R^T R from
 //         v = (1, ..., 1) / sqrt(k) (0 if ||A||_F or s1 is 0): the stable rank of A seen through the
 //         probe, which keeps growing where the 16 diagonal entries no longer resolve a slow decay.
-__global__ void features_kernel(const FeatDesc *__restrict__ d, int count, float *__restrict__ feats) {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= count) return;
-    const FeatDesc D = d[b];
-    float *f = feats + (size_t)D.out * MLP_IN;
-    f[0] = (float)(log2((double)D.m) / 9.0);
-    f[1] = (float)(log2((double)D.n) / 9.0);
-    const double r0 = fabs(D.R[0]);
-    for (int i = 1; i < MLP_IN - 2; ++i) {
-        double v = -20.0;
-        if (i < D.k && r0 > 0.0) {
-            const double ri = fabs(D.R[i + (size_t)i * D.ldr]);
-            v = ri > 0.0 ? fmax(log10(ri / r0), -20.0) : -20.0;
-        }
-        f[1 + i] = (float)(v / 16.0);
+// Sixteen lanes per block (four blocks per wave): lane i keeps row i and column i of R in registers,
+// so each power step is two triangular products whose other operand (v, then w = R v) comes from
+// the group's lanes by shuffles, and the norm is a DPP group sum. The products run over j in
+// ascending order as in the plain loops (zero entries outside the triangle add nothing).
+__global__ __launch_bounds__(64) void features_kernel(const FeatDesc *__restrict__ d, int count,
+                                                      float *__restrict__ feats) {
+    constexpr int K = PROBE_COLS;
+    static_assert(K == 16, "one DPP row of lanes per block");
+    const int lane = threadIdx.x;
+    const int grp = lane >> 4, i = lane & 15, base = lane & ~15;
+    const int b = blockIdx.x * 4 + grp;
+    const bool act = b < count;
+    FeatDesc D{};
+    if (act) D = d[b];
+    const int k = act ? D.k : 0;
+    double rrow[K], rcol[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        rrow[j] = (i < k && j >= i && j < k) ? D.R[i + (size_t)j * D.ldr] : 0.0;
+        rcol[j] = (i < k && j <= i) ? D.R[j + (size_t)i * D.ldr] : 0.0;
     }
-    double a2 = 0.0;
-    for (int t = 0; t < D.ntile; ++t) a2 += D.xsq[2 * t] + D.xsq[2 * t + 1];
-    const int k = D.k;
-    double v[PROBE_COLS], w[PROBE_COLS];
-    for (int i = 0; i < k; ++i) v[i] = 1.0 / sqrt((double)k);
-    for (int it = 0; it < 64; ++it) {
-        for (int i = 0; i < k; ++i) {
-            double s = 0.0;
-            for (int j = i; j < k; ++j) s += D.R[i + (size_t)j * D.ldr] * v[j];
-            w[i] = s;
-        }
-        double nz = 0.0;
-        for (int j = 0; j < k; ++j) {
-            double s = 0.0;
-            for (int i = 0; i <= j; ++i) s += D.R[i + (size_t)j * D.ldr] * w[i];
-            v[j] = s;
-            nz += s * s;
-        }
-        nz = sqrt(nz);
-        if (!(nz > 0.0)) break;
-        for (int j = 0; j < k; ++j) v[j] /= nz;
-    }
-    double s1 = 0.0;
-    for (int i = 0; i < k; ++i) {
+    double v = (i < k) ? 1.0 / sqrt((double)k) : 0.0;
+    for (int it = 0; it < 64 && k > 0; ++it) {
+        double w = 0.0;
+#pragma unroll
+        for (int j = 0; j < K; ++j) w += rrow[j] * __shfl(v, base + j, 64);
         double s = 0.0;
-        for (int j = i; j < k; ++j) s += D.R[i + (size_t)j * D.ldr] * v[j];
-        s1 += s * s;
+#pragma unroll
+        for (int j = 0; j < K; ++j) s += rcol[j] * __shfl(w, base + j, 64);
+        const double nz = sqrt(group_sum<16>(s * s));
+        if (!(nz > 0.0)) break;  // the same in every lane of the group
+        v = s / nz;
     }
-    f[MLP_IN - 1] = (a2 > 0.0 && s1 > 0.0) ? (float)(log2((double)k * a2 / s1) / 8.0) : 0.0f;
+    double w = 0.0;
+#pragma unroll
+    for (int j = 0; j < K; ++j) w += rrow[j] * __shfl(v, base + j, 64);
+    const double s1 = group_sum<16>(w * w);
+    if (!act) return;
+    float *f = feats + (size_t)D.out * MLP_IN;
+    if (i == 0) {
+        f[0] = (float)(log2((double)D.m) / 9.0);
+        f[1] = (float)(log2((double)D.n) / 9.0);
+        double a2 = 0.0;
+        for (int t = 0; t < D.ntile; ++t) a2 += D.xsq[2 * t] + D.xsq[2 * t + 1];
+        f[MLP_IN - 1] = (a2 > 0.0 && s1 > 0.0) ? (float)(log2((double)k * a2 / s1) / 8.0) : 0.0f;
+    } else if (i < MLP_IN - 2) {
+        double val = -20.0;
+        const double r0 = fabs(D.R[0]);
+        if (i < k && r0 > 0.0) {
+            const double ri = fabs(D.R[i + (size_t)i * D.ldr]);
+            val = ri > 0.0 ? fmax(log10(ri / r0), -20.0) : -20.0;
+        }
+        f[1 + i] = (float)(val / 16.0);
+    }
 }
 
 __global__ void mlp_init_kernel(float *__restrict__ p, unsigned long long seed) {
@@ -251,7 +261,7 @@ hipError_t launch_mlp_init(float *p, unsigned long long seed, hipStream_t st) {
 
 hipError_t launch_features(const FeatDesc *d, int count, float *feats, hipStream_t st) {
     if (count <= 0) return hipSuccess;
-    hipLaunchKernelGGL(features_kernel, dim3(nb256(count)), dim3(256), 0, st, d, count, feats);
+    hipLaunchKernelGGL(features_kernel, dim3((count + 3) / 4), dim3(64), 0, st, d, count, feats);
     return hipGetLastError();
 }
 
