@@ -53,14 +53,15 @@ __global__ __launch_bounds__(256) void bj_init_kernel(const BjMat *__restrict__ 
 __device__ __forceinline__ int bj_col(const BjTask &t, int a, int w) { return a < w ? t.p * w + a : t.q * w + (a - w); }
 
 // G = Wpq^T Wpq with K = 2w; 256 threads = 4 waves; wave v computes output tiles (ti, tj) with
-// ti * (K/16) + tj == v (mod 4). Rows are staged in chunks of 16 through LDS (coalesced loads).
+// ti * (K/16) + tj == v (mod 4). Rows are staged in chunks of 16 (32 at K = 64) through LDS
+// (coalesced loads, one memory round trip per chunk; larger chunks cost residency at K <= 32).
 template <typename T, int W_>
 __global__ __launch_bounds__(256) void bj_gram_kernel(const BjMat *__restrict__ mats, const BjTask *__restrict__ tasks,
                                                       double tol) {
     constexpr int K = 2 * W_;
     constexpr int NT = K / 16;           // tiles per dimension
     constexpr int TPW = NT * NT / 4 > 0 ? NT * NT / 4 : 1;  // tiles per wave
-    constexpr int RC = 16;               // rows per chunk
+    constexpr int RC = K >= 64 ? 32 : 16;  // rows per chunk staged in LDS (one round trip each)
     __shared__ double xs[RC][K + 1];
     __shared__ double gsh[K][K + 1];
     __shared__ double emax[256];
@@ -133,13 +134,16 @@ __global__ __launch_bounds__(256) void bj_gram_kernel(const BjMat *__restrict__ 
     }
 }
 
-// [X_p X_q] <- [X_p X_q] V_G for X = W (M rows) and X = V (NP rows), in place. Each wave owns
-// 16-row tiles: it reads the tile's K columns, multiplies by V_G (staged in LDS) on MFMA, and
-// writes the tile back after all of its reads.
+// [X_p X_q] <- [X_p X_q] V_G for X = W (M rows) and X = V (NP rows), in place. Each wave owns groups
+// of TB 16-row tiles (128 / K tiles, so that a group's reads fill 32 registers per lane): it issues
+// every read of the group first, then multiplies tile by tile by V_G (staged in LDS) on MFMA and
+// writes each tile back; the group's reads are all in flight together.
 template <typename T, int W_>
 __global__ __launch_bounds__(256) void bj_apply_kernel(const BjMat *__restrict__ mats, const BjTask *__restrict__ tasks) {
     constexpr int K = 2 * W_;
     constexpr int NT = K / 16;
+    constexpr int KS = K / 4;
+    constexpr int TB = (K >= 128 || (sizeof(T) == 4 && K >= 64)) ? 1 : 128 / K;
     __shared__ double vg[K][K + 1];
     const BjTask t = tasks[blockIdx.x];
     if (t.state[1] == 0.0) return;  // pair already orthogonal to tolerance
@@ -155,27 +159,38 @@ __global__ __launch_bounds__(256) void bj_apply_kernel(const BjMat *__restrict__
         T *X = static_cast<T *>(which == 0 ? B.W : B.V);
         const int rows = which == 0 ? B.M : B.NP;
         const int ntile = (rows + 15) / 16;
-        for (int rt = wave; rt < ntile; rt += 4) {
-            const int r = rt * 16 + (l % 16);
-            const bool rok = r < rows;
-            d4_t acc[NT];
+        const int ngroup = (ntile + TB - 1) / TB;
+        for (int gi = wave; gi < ngroup; gi += 4) {
+            double a[TB][KS];
 #pragma unroll
-            for (int j = 0; j < NT; ++j) acc[j] = d4_t{0.0, 0.0, 0.0, 0.0};
+            for (int tb = 0; tb < TB; ++tb) {
+                const int r = (gi * TB + tb) * 16 + (l % 16);
+                const bool rok = r < rows;
 #pragma unroll
-            for (int k0 = 0; k0 < K; k0 += 4) {
-                const int kk = k0 + l / 16;
-                const double a = rok ? (double)X[r + (size_t)bj_col(t, kk, W_) * rows] : 0.0;
-#pragma unroll
-                for (int j = 0; j < NT; ++j) acc[j] = mfma_f64(a, vg[kk][j * 16 + (l % 16)], acc[j]);
+                for (int s = 0; s < KS; ++s)
+                    a[tb][s] = rok ? (double)X[r + (size_t)bj_col(t, 4 * s + l / 16, W_) * rows] : 0.0;
             }
-            // lane holds rows l/16 + 4 q of output column j*16 + l%16 of this row tile
 #pragma unroll
-            for (int j = 0; j < NT; ++j) {
-                const int col = bj_col(t, j * 16 + (l % 16), W_);
+            for (int tb = 0; tb < TB; ++tb) {
+                d4_t acc[NT];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int rr = rt * 16 + (l / 16) + 4 * q;
-                    if (rr < rows) X[rr + (size_t)col * rows] = (T)acc[j][q];
+                for (int j = 0; j < NT; ++j) acc[j] = d4_t{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int s = 0; s < KS; ++s) {
+                    const int kk = 4 * s + l / 16;
+#pragma unroll
+                    for (int j = 0; j < NT; ++j) acc[j] = mfma_f64(a[tb][s], vg[kk][j * 16 + (l % 16)], acc[j]);
+                }
+                // lane holds rows l/16 + 4 q of output column j*16 + l%16 of this row tile
+                const int rt = gi * TB + tb;
+#pragma unroll
+                for (int j = 0; j < NT; ++j) {
+                    const int col = bj_col(t, j * 16 + (l % 16), W_);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int rr = rt * 16 + (l / 16) + 4 * q;
+                        if (rr < rows) X[rr + (size_t)col * rows] = (T)acc[j][q];
+                    }
                 }
             }
         }
