@@ -115,7 +115,7 @@ int block_jacobi_run(Ctx *c, int dtype, int w, const std::vector<int> &insts, co
 
     std::vector<int> active(nm);
     for (int i = 0; i < nm; ++i) active[i] = i;
-    std::vector<int> app_rec(rot_ld, -1);
+    std::vector<int> app_rec(rot_ld, -1), inner_rec(rot_ld, -1);
     // The block rotation of a pair comes from at most two sweeps of the inner one-sided Jacobi on G:
     // an orthogonal matrix that removes most of G's off-diagonal mass (all of it once the pair is
     // nearly orthogonal, where Jacobi converges quadratically). The outer test is unchanged -- every
@@ -124,6 +124,7 @@ int block_jacobi_run(Ctx *c, int dtype, int w, const std::vector<int> &insts, co
     const int inner_sweeps = BJ_INNER_SWEEPS;
     for (int sw = 0; sw < max_sweeps && !active.empty(); ++sw) {
         std::fill(app_rec.begin(), app_rec.end(), -1);
+        std::fill(inner_rec.begin(), inner_rec.end(), -1);
         for (int s = 0; s < nbmax - 1; ++s) {
             // tasks of this step
             if ((rc = c->ensure_host(dsz))) return rc;
@@ -207,6 +208,7 @@ int block_jacobi_run(Ctx *c, int dtype, int w, const std::vector<int> &insts, co
                 e = launch_jacobi_lds(0, jk.a, jk.b, dsd, dl, (int)ntask, 1e-15, inner_sweeps, nullptr, nullptr, c->stream);
             if (e != hipSuccess) return c->hip_fail(e, "block inner svd launch");
             c->prof_end(pi, 0.0, 0.0);
+            inner_rec[s] = pi;
             std::snprintf(tag, sizeof tag, "bj_apply_kernel<%s, %d>", tname, w);
             pi = c->prof_begin(BSVD_STAGE_JACOBI, tag);
             e = launch_bj_apply(dtype, w, dmats, dt, (int)ntask, c->stream);
@@ -249,6 +251,16 @@ int block_jacobi_run(Ctx *c, int dtype, int w, const std::vector<int> &insts, co
                 }
                 c->recs[app_rec[s]].bytes = by;
                 c->recs[app_rec[s]].flops = fl;
+                // model: the inner SVD of a rotated pair runs both of its sweeps (a Gram measure
+                // above tol makes the first sweep rotate, so the second one runs); skipped pairs do
+                // nothing. G read, V_G written.
+                if (inner_rec[s] >= 0) {
+                    double cnt = 0.0;
+                    for (size_t j = 0; j < active.size(); ++j)
+                        if (s < hm[active[j]].nb - 1) cnt += rot[j * rot_ld + s];
+                    c->recs[inner_rec[s]].bytes = cnt * 2.0 * 8.0 * K * K;
+                    c->recs[inner_rec[s]].flops = cnt * jacobi_flops(K, K, inner_sweeps);
+                }
             }
         }
         std::vector<int> still, done;
