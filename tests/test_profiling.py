@@ -1,0 +1,62 @@
+"""CPU tests of the rocprofv3 summary helpers (paper_1707_05141_amd.profiling) on small synthetic
+CSV files laid out as rocprofv3 writes them."""
+import csv
+import os
+
+import pytest
+
+from paper_1707_05141_amd import profiling
+
+
+def _write(path, header, rows):
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    with open(path, "w", newline="") as f:
+        w = csv.writer(f)
+        w.writerow(header)
+        w.writerows(rows)
+
+
+def test_kernel_name_matching():
+    assert profiling.matches("void bsvd::bj_apply_kernel<double, 16>(bsvd::BjMat const*, bsvd::BjTask const*)",
+                             "bj_apply_kernel<double, 16>")
+    assert not profiling.matches("void bsvd::bj_apply_kernel<double, 8>(bsvd::BjMat const*)", "bj_apply_kernel<double, 16>")
+    assert profiling.matches("bsvd::features_kernel(bsvd::FeatDesc const*, int, float*)", "features_kernel")
+    assert not profiling.matches("void bsvd::jacobi_lds_kernel<double, 64, 64>(x)", "jacobi_lds")
+
+
+def test_trace_window_averages_last_dispatches(tmp_path):
+    k = "void bsvd::k<double, 16>(int)"
+    rows = []
+    t = 1000
+    for i in range(10):  # durations 1..10 us, in start order; another kernel interleaved
+        rows.append(["KERNEL_DISPATCH", i, k, t, t + 1000 * (i + 1)])
+        rows.append(["KERNEL_DISPATCH", 100 + i, "void bsvd::other(int)", t + 50, t + 60])
+        t += 100000
+    _write(str(tmp_path / "run" / "x_kernel_trace.csv"),
+           ["Kind", "Dispatch_Id", "Kernel_Name", "Start_Timestamp", "End_Timestamp"], rows)
+    r = profiling.trace(str(tmp_path), "k<double, 16>", 4)
+    assert r["dispatches"] == 10 and r["last_n"] == 4
+    assert r["last_n_avg_ms"] == pytest.approx((7 + 8 + 9 + 10) / 4 * 1e-3)
+    assert r["all_avg_ms"] == pytest.approx(5.5e-3)
+
+
+def test_pmc_scaled_by_copy_calibration(tmp_path):
+    k = "void bsvd::k<double, 16>(int)"
+    hdr = ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"]
+    # kernel: first two dispatches (warm-up) differ from the last three (timed)
+    _write(str(tmp_path / "f" / "a_counter_collection.csv"), hdr,
+           [[1, k, "FETCH_SIZE", 999.0], [2, k, "FETCH_SIZE", 999.0], [3, k, "FETCH_SIZE", 100.0],
+            [4, k, "FETCH_SIZE", 110.0], [5, k, "FETCH_SIZE", 120.0]])
+    _write(str(tmp_path / "w" / "a_counter_collection.csv"), hdr,
+           [[1, k, "WRITE_SIZE", 1.0], [3, k, "WRITE_SIZE", 300.0], [4, k, "WRITE_SIZE", 300.0], [5, k, "WRITE_SIZE", 300.0]])
+    # copy of 1 MiB: a fill first (reads nothing), then five copies; the fetch counter reads half
+    c = "void at::native::copy(int)"
+    _write(str(tmp_path / "cf" / "a_counter_collection.csv"), hdr,
+           [[1, "void at::native::fill(int)", "FETCH_SIZE", 0.0]] + [[2 + i, c, "FETCH_SIZE", 512.0] for i in range(5)])
+    _write(str(tmp_path / "cw" / "a_counter_collection.csv"), hdr,
+           [[1, "void at::native::fill(int)", "WRITE_SIZE", 1024.0]] + [[2 + i, c, "WRITE_SIZE", 1024.0] for i in range(5)])
+    r = profiling.pmc(str(tmp_path / "f"), str(tmp_path / "w"), str(tmp_path / "cf"), str(tmp_path / "cw"), 1.0,
+                      "k<double, 16>", 3)
+    assert r["fetch_scale"] == pytest.approx(2.0) and r["write_scale"] == pytest.approx(1.0)
+    assert r["fetch_kib"] == pytest.approx(110.0) and r["write_kib"] == pytest.approx(300.0)
+    assert r["bytes_per_dispatch"] == pytest.approx(1024.0 * (2.0 * 110.0 + 300.0))
