@@ -205,14 +205,17 @@ int batched_qr(bsvd_ctx *ctx, int dtype, int batch, const int *m, const int *n, 
  * drawn, projected against the current basis twice (classical Gram-Schmidt), and the mean squared
  * norm of the projected samples -- an unbiased estimate of ||(I - Q Q^T) A||_F^2 -- stops the
  * growth once it is <= (eps / 2)^2 ||A||_F^2; the orthonormalised block is always appended. The exact
- * test ||A||_F^2 - ||Q^T A||_F^2 <= eps^2 ||A||_F^2 (eps^2 / 4 with LEARNED or MIXED, whose first
- * samples did not come from the estimator) then accepts the basis or resumes growth. The basis is
- * capped at min(m, n, max_rank + 32) columns. Bases wider than 64 columns are orthonormalised panel
- * by panel (blocked Gram-Schmidt with reorthogonalisation) and R_B is diagonalised by the block
- * Jacobi method (Section 6.1). ||A||_F^2 and ||B||_F^2 are summed in double-double arithmetic, and
- * the truncation residual is ||A||_F^2 - ||B||_F^2 (not ||A||_F^2 - sum sigma^2). A batch whose
- * workspace would exceed 96 GiB (or half the free device memory) runs in consecutive sub-batches
- * with identical results.
+ * test ||A||_F^2 - ||Q^T A||_F^2 <= eps^2 ||A||_F^2 (eps^2 / 4 with LEARNED or MIXED until an FP64
+ * block has been grown under the estimator, since their first samples did not come from it) then
+ * accepts the basis or resumes growth. The basis is capped at min(m, n, max_rank + 32) columns.
+ * Bases wider than 64 columns are orthonormalised panel by panel (blocked Gram-Schmidt with
+ * reorthogonalisation); their R_B is diagonalised by the single-kernel LDS Jacobi (up to 128 columns)
+ * or the block Jacobi method (Section 6.1), as the autotuner chooses per size class.
+ * ||A||_F^2 and ||B||_F^2 are summed in double-double arithmetic, and the truncation residual is
+ * ||A||_F^2 - ||B||_F^2 (not ||A||_F^2 - sum sigma^2). A batch whose workspace would exceed 96 GiB
+ * (or half the free device memory) runs in consecutive sub-batches with identical results.
+ * Two environment variables serve tests: BSVD_RSVD_BUDGET_MB lowers the workspace bound (to force
+ * sub-batches), BSVD_RB_WIDTH (0, 8, 16 or 32) fixes the R_B path instead of the autotuner.
  *
  * Omega's entry (row r, column j) of instance b is N(0,1) from Philox4x32-10 with counter
  * (r, j, b, 0) and key (seed low, seed high), mapped by Box-Muller; column indices continue across
