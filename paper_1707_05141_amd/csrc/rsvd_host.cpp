@@ -974,7 +974,7 @@ static int rsvd_range(Ctx *c, int inst_base, int batch, const int *m, const int 
             std::copy(kv.second.begin(), kv.second.end(), hjl);
             jl.push_back({kv.first, {djl, (int)kv.second.size()}});
         }
-        // 65..96 columns: V in LDS; 97..128: V in global memory
+        // 65..96 columns: V in LDS; 97..128: V in registers
         std::vector<int> wide_lo, wide_hi;
         for (int i : wide_pos) (I[finished[i]].ell <= 96 ? wide_lo : wide_hi).push_back(i);
         int *dwl_lo = nullptr, *dwl_hi = nullptr;
